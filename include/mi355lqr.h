@@ -1,0 +1,174 @@
+/*
+ * mi355lqr.h -- C ABI of the MI355X (gfx950) parallel Riccati LQR solver.
+ *
+ * Problem solved (Laine & Tomlin, "The Parallelization of Riccati Recursion",
+ * arXiv:1809.06360, Sec. II, problem (opt:globalwords) with the costs of
+ * eq. (costtform) and the dynamics of eq. (dynamicsform)):
+ *
+ *   minimise  sum_{t<T} [ 1/2 x_t'Q_t x_t + u_t'S_t x_t + 1/2 u_t'R_t u_t
+ *                          + q_t'x_t + r_t'u_t ]  +  1/2 x_T'Q_T x_T + q_T'x_T
+ *   s.t.      x_{t+1} = A_t x_t + B_t u_t + c_t,   x_0 = x0.
+ *
+ * (Paper symbols: Q_xx = Q, Q_ux = S, Q_uu = R, q_x1 = q, q_u1 = r, F_x = A,
+ * F_u = B, f_1 = c.) The un-halved objective sum x'Qx + u'Ru + 2q'x + 2r'u is
+ * twice this one and has the same minimiser. The problem must be strictly
+ * convex: R_t positive definite and Q_t - S_t'R_t^{-1}S_t positive
+ * semidefinite (the assumption stated after eq. dynamicsform).
+ *
+ * Outputs are the serial-Riccati feedback policy u_t = K_t x_t + k_t (the sign
+ * of eq. controlpolicy), the value function 1/2 x'P_t x + p_t'x (cost-to-go,
+ * eq. costtogo without the x_term block), the optimal trajectory (x_t, u_t)
+ * and, optionally, the costate lam_t = P_t x_t + p_t (minus the paper's
+ * multiplier lambda_t of eq. KKT). The parallel algorithm splits the horizon
+ * into J segments (Sec. II-A), solves every segment as an affine function of
+ * its unknown end state, solves the small system linking the segments
+ * (Sec. II-A, link equation, and its J-segment generalisation) and rebuilds
+ * the per-stage results; all results equal the serial recursion's up to
+ * rounding (Sec. III-A).
+ *
+ * Conventions for every entry point:
+ *  - Arrays are row-major and time-major. Pointers inside lqr_problem_t and
+ *    lqr_grad_t are DEVICE pointers (HBM of the current HIP device); the
+ *    structs themselves and the arrays of structs are HOST memory and may be
+ *    reused as soon as the call returns.
+ *  - Element type is double for LQR_PREC_FP64 and LQR_PREC_MIXED and float for
+ *    LQR_PREC_FP32.
+ *  - The caller owns every buffer, including the workspace. The library
+ *    allocates no device memory, never synchronises the stream, prints
+ *    nothing, and lets no C++ exception cross the ABI.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and runs asynchronously. Argument errors are returned synchronously;
+ *    numerical failures are written asynchronously to the instance's `info`.
+ *  - Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef MI355LQR_H
+#define MI355LQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LQR_SUCCESS = 0,
+    LQR_ERR_INVALID_ARG = 1,      /* bad size, NULL required pointer, segments out of range */
+    LQR_ERR_NOT_PD = 2,           /* reserved for callers that turn `info` into a status */
+    LQR_ERR_SINGULAR_COUPLING = 3,/* reserved, as above */
+    LQR_ERR_NONFINITE = 4,        /* reserved, as above */
+    LQR_ERR_WORKSPACE = 5,        /* workspace NULL or smaller than lqr_workspace_size */
+    LQR_ERR_HIP = 6,              /* a HIP runtime call failed (launch, copy) */
+    LQR_ERR_UNSUPPORTED = 7       /* valid problem that this build cannot run (size, mode) */
+} lqr_status_t;
+
+typedef enum {
+    LQR_PREC_FP64 = 0,   /* everything in double */
+    LQR_PREC_MIXED = 1,  /* double I/O; bulk products in float on MFMA with float
+                            accumulation; factorizations and the linking solve in double */
+    LQR_PREC_FP32 = 2    /* everything in float */
+} lqr_precision_t;
+
+typedef enum {
+    LQR_ALGO_PARALLEL = 0, /* segment sweeps, linking solve, per-segment rebuild (Sec. II-A) */
+    LQR_ALGO_SERIAL = 1    /* one plain Riccati recursion over the whole horizon per instance */
+} lqr_algo_t;
+
+/* info codes (per instance, device int32, written asynchronously):
+ *   0                         success
+ *   t + 1  (1 <= info <= T)   the input Hessian R_t + B_t'P B_t (+ terms) of
+ *                             stage t failed its Cholesky factorization (pivot
+ *                             not positive or not finite); when several stages
+ *                             fail, the largest such t is reported. The
+ *                             instance's outputs are then NaN from that stage on.
+ *   LQR_INFO_COUPLING + j     the linking system at segment boundary j had a
+ *                             zero or non-finite pivot.                        */
+#define LQR_INFO_COUPLING 0x40000000
+
+/* One LQR instance. */
+typedef struct {
+    int32_t n, m, T;       /* state dim, input dim, horizon; all >= 1 */
+    int32_t segments;      /* J, 1 <= J <= T; 0 = let the planner choose */
+    const void *A;         /* [T][n][n]   dynamics, state                                 */
+    const void *B;         /* [T][n][m]   dynamics, input                                 */
+    const void *c;         /* [T][n]      dynamics, offset                                */
+    const void *Q;         /* [T+1][n][n] state cost; index T is the terminal cost        */
+    const void *q;         /* [T+1][n]    linear state cost; index T terminal             */
+    const void *R;         /* [T][m][m]   input cost (symmetric positive definite)        */
+    const void *r;         /* [T][m]      linear input cost                               */
+    const void *S;         /* [T][m][n]   cross cost u'S x, or NULL for zero             */
+    const void *x0;        /* [n]         initial state                                   */
+    void *K;               /* [T][m][n]   out: feedback gains                     (required) */
+    void *k;               /* [T][m]      out: feedforward terms                  (required) */
+    void *P;               /* [T+1][n][n] out: value Hessians       (NULL = not written) */
+    void *p;               /* [T+1][n]    out: value gradients      (NULL = not written) */
+    void *x;               /* [T+1][n]    out: optimal states                     (required) */
+    void *u;               /* [T][m]      out: optimal inputs                     (required) */
+    void *lam;             /* [T+1][n]    out: costates P_t x_t + p_t (NULL = not written) */
+    void *chol;            /* [T][m][m]   out: lower Cholesky factor of each stage's input
+                                          Hessian, zero above the diagonal (NULL = not
+                                          written); lqr_backward needs it              */
+    int32_t *info;         /* [1] device int32, see the info codes above          (required) */
+} lqr_problem_t;
+
+typedef struct {
+    lqr_precision_t precision;
+    lqr_algo_t algo;
+    uint32_t flags;        /* must be 0 */
+} lqr_options_t;
+
+/* Upstream gradients and gradient outputs of lqr_backward (device pointers). */
+typedef struct {
+    const void *dl_dx;     /* [T+1][n] dloss/dx_t   (required) */
+    const void *dl_du;     /* [T][m]   dloss/du_t   (required) */
+    void *dA, *dB, *dc;    /* shapes of A, B, c; NULL = not written */
+    void *dQ, *dq;         /* shapes of Q, q (symmetric-form gradient for Q) */
+    void *dR, *dr;         /* shapes of R, r (symmetric-form gradient for R) */
+    void *dS;              /* shape of S ([T][m][n]) */
+    void *dx0;             /* [n] */
+} lqr_grad_t;
+
+/* Bytes of device workspace that lqr_solve / lqr_solve_batched / lqr_backward
+ * need for these problems and options (probs: HOST array of `batch`
+ * descriptors; only n, m, T and segments are read). The same size serves all
+ * three calls. Writes the size to *bytes (host). */
+lqr_status_t lqr_workspace_size(const lqr_problem_t *probs, int32_t batch,
+                                const lqr_options_t *opts, size_t *bytes);
+
+/* Solve one instance (prob: HOST pointer to one descriptor). `ws` is a device
+ * buffer of at least lqr_workspace_size bytes, 256-byte aligned; its contents
+ * need no initialisation and are overwritten. */
+lqr_status_t lqr_solve(const lqr_problem_t *prob, const lqr_options_t *opts,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Solve `batch` independent instances of possibly different n, m, T in one
+ * launch sequence. The execution plan (per-instance segment counts and the
+ * work-item table) is built on the host and copied into the workspace; when a
+ * call is made while `stream` is being captured into a HIP graph, the plan for
+ * exactly these descriptors must already be in this workspace from an earlier,
+ * uncaptured call (else LQR_ERR_INVALID_ARG), and the call then only launches
+ * kernels. */
+lqr_status_t lqr_solve_batched(const lqr_problem_t *probs, int32_t batch,
+                               const lqr_options_t *opts, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* Gradient of a scalar loss l(x, u) of the solution with respect to the
+ * problem data, by implicit differentiation of the KKT system (eq. KKT): the
+ * same LQR is re-solved with linear terms -dl/dx, -dl/du, zero offsets and a
+ * zero initial state (the KKT matrix is symmetric, so its transpose is
+ * itself), reusing the forward gains and factorizations, and the gradients
+ * are outer products of the two solutions. probs[i] must hold the forward
+ * data and the forward outputs K, P, x, u, lam and chol of the same call
+ * sequence; grads[i] the upstream gradients and the outputs. */
+lqr_status_t lqr_backward(const lqr_problem_t *probs, int32_t batch,
+                          const lqr_grad_t *grads, const lqr_options_t *opts,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *lqr_status_string(lqr_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355LQR_H */

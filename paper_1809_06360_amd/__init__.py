@@ -1,0 +1,233 @@
+"""MI355X-native parallel Riccati recursion for time-varying finite-horizon LQR.
+
+Thin Python binding of the C ABI in ``include/mi355lqr.h`` (library
+``libmi355lqr.so``, built in-tree for gfx950 by ``paper_1809_06360_amd.build``).
+The functions ``lqr_workspace_size``, ``lqr_solve``, ``lqr_solve_batched``,
+``lqr_backward`` and ``lqr_status_string`` mirror the C entry points and only
+marshal arguments; every step of the solve runs in the library's HIP kernels.
+PyTorch supplies device memory and the current stream.
+
+There is no CPU fallback: if the library has not been built, loading it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "LIB_PATH", "library", "LqrProblem", "LqrOptions", "LqrGrad",
+    "lqr_workspace_size", "lqr_solve", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
+    "solve", "solve_batched", "LQRError",
+    "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
+    "INFO_COUPLING",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi355lqr.so")
+
+SUCCESS, ERR_INVALID_ARG, ERR_NOT_PD, ERR_SINGULAR_COUPLING = 0, 1, 2, 3
+ERR_NONFINITE, ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = 4, 5, 6, 7
+PREC_FP64, PREC_MIXED, PREC_FP32 = 0, 1, 2
+ALGO_PARALLEL, ALGO_SERIAL = 0, 1
+INFO_COUPLING = 0x40000000
+
+_vp = ctypes.c_void_p
+
+
+class LqrProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("segments", ctypes.c_int32)] + \
+               [(name, _vp) for name in ("A", "B", "c", "Q", "q", "R", "r", "S", "x0",
+                                         "K", "k", "P", "p", "x", "u", "lam", "chol", "info")]
+
+
+class LqrOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("algo", ctypes.c_int), ("flags", ctypes.c_uint32)]
+
+
+class LqrGrad(ctypes.Structure):
+    _fields_ = [(name, _vp) for name in ("dl_dx", "dl_du", "dA", "dB", "dc", "dQ", "dq",
+                                         "dR", "dr", "dS", "dx0")]
+
+
+EXPORTS = ("lqr_workspace_size", "lqr_solve", "lqr_solve_batched", "lqr_backward",
+           "lqr_status_string")
+
+_lib = None
+
+
+class LQRError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (where, lqr_status_string(status), status))
+
+
+def library():
+    """Load ``libmi355lqr.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmi355lqr.so is not built; run `python -m paper_1809_06360_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        lib.lqr_workspace_size.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), P(ctypes.c_size_t)]
+        lib.lqr_workspace_size.restype = ctypes.c_int
+        lib.lqr_solve.argtypes = [P(LqrProblem), P(LqrOptions), _vp, ctypes.c_size_t, _vp]
+        lib.lqr_solve.restype = ctypes.c_int
+        lib.lqr_solve_batched.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), _vp,
+                                          ctypes.c_size_t, _vp]
+        lib.lqr_solve_batched.restype = ctypes.c_int
+        lib.lqr_backward.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrGrad), P(LqrOptions), _vp,
+                                     ctypes.c_size_t, _vp]
+        lib.lqr_backward.restype = ctypes.c_int
+        lib.lqr_status_string.argtypes = [ctypes.c_int]
+        lib.lqr_status_string.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# C entry points, same names and arguments (structs by ctypes pointer/array).
+# ---------------------------------------------------------------------------
+def lqr_status_string(status: int) -> str:
+    return library().lqr_status_string(int(status)).decode()
+
+
+def lqr_workspace_size(probs, batch: int, opts: LqrOptions) -> int:
+    out = ctypes.c_size_t(0)
+    st = library().lqr_workspace_size(probs, int(batch), ctypes.byref(opts), ctypes.byref(out))
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_workspace_size")
+    return int(out.value)
+
+
+def lqr_solve(prob: LqrProblem, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:
+    st = library().lqr_solve(ctypes.byref(prob), ctypes.byref(opts), ws, ws_bytes, stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_solve")
+
+
+def lqr_solve_batched(probs, batch: int, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:
+    st = library().lqr_solve_batched(probs, int(batch), ctypes.byref(opts), ws, ws_bytes, stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_solve_batched")
+
+
+def lqr_backward(probs, batch: int, grads, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:
+    st = library().lqr_backward(probs, int(batch), grads, ctypes.byref(opts), ws, ws_bytes, stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_backward")
+
+
+# ---------------------------------------------------------------------------
+# Tensor-level convenience wrappers (marshalling only).
+# ---------------------------------------------------------------------------
+_PREC = {"fp64": PREC_FP64, "mixed": PREC_MIXED, "fp32": PREC_FP32}
+_ALGO = {"parallel": ALGO_PARALLEL, "serial": ALGO_SERIAL}
+INPUTS = ("A", "B", "c", "Q", "q", "R", "r", "x0")
+
+
+def options(precision: str = "fp64", algo: str = "parallel") -> LqrOptions:
+    return LqrOptions(_PREC[precision], _ALGO[algo], 0)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check_input(name, t, shape, dtype, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dtype, device))
+
+
+def _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol):
+    import torch
+    e = lambda *s: torch.empty(*s, dtype=dtype, device=device)  # noqa: E731
+    out = dict(K=e(T, m, n), k=e(T, m), x=e(T + 1, n), u=e(T, m),
+               info=torch.zeros(1, dtype=torch.int32, device=device))
+    if with_P or with_lam:
+        out["P"] = e(T + 1, n, n)
+        out["p"] = e(T + 1, n)
+    if with_lam:
+        out["lam"] = e(T + 1, n)
+    if with_chol:
+        out["chol"] = e(T, m, m)
+    return out
+
+
+def _problem(data: dict, out: dict, segments: int) -> LqrProblem:
+    T, n, m = data["B"].shape
+    return LqrProblem(n, m, T, int(segments),
+                      _ptr(data["A"]), _ptr(data["B"]), _ptr(data["c"]), _ptr(data["Q"]),
+                      _ptr(data["q"]), _ptr(data["R"]), _ptr(data["r"]), _ptr(data.get("S")),
+                      _ptr(data["x0"]), _ptr(out["K"]), _ptr(out["k"]), _ptr(out.get("P")),
+                      _ptr(out.get("p")), _ptr(out["x"]), _ptr(out["u"]), _ptr(out.get("lam")),
+                      _ptr(out.get("chol")), _ptr(out["info"]))
+
+
+def _validate(data: dict, dtype, device):
+    T, n, m = data["B"].shape
+    shapes = dict(A=(T, n, n), B=(T, n, m), c=(T, n), Q=(T + 1, n, n), q=(T + 1, n),
+                  R=(T, m, m), r=(T, m), x0=(n,), S=(T, m, n))
+    for key in INPUTS + ("S",):
+        if key == "S" and data.get("S") is None:
+            continue
+        _check_input(key, data[key], shapes[key], dtype, device)
+    return int(n), int(m), int(T)
+
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def solve(data: dict, segments: int = 0, precision: str = "fp64", algo: str = "parallel",
+          with_P: bool = True, with_lam: bool = True, with_chol: bool = False,
+          workspace=None, stream=None) -> dict:
+    """Solve one LQR instance given as a dict of device tensors (A, B, c, Q, q,
+    R, r, x0 and optionally S; float64). Returns a dict of output tensors
+    (K, k, P, p, x, u, lam, chol, info). Asynchronous on the current stream."""
+    import torch
+    dtype = torch.float32 if precision == "fp32" else torch.float64
+    device = data["A"].device
+    n, m, T = _validate(data, dtype, device)
+    out = _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol)
+    prob = _problem(data, out, segments)
+    opts = options(precision, algo)
+    nbytes = lqr_workspace_size(ctypes.byref(prob), 1, opts)
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    lqr_solve(prob, opts, ws.data_ptr(), ws.numel(), s)
+    out["_workspace"] = ws
+    return out
+
+
+def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "parallel",
+                  with_P: bool = True, with_lam: bool = True, with_chol: bool = False,
+                  workspace=None, stream=None, outputs=None):
+    """Solve a list of instances (dicts of device tensors, possibly different
+    n, m, T) with one batched call. ``segments``: None (planner) or a list of
+    per-instance segment counts. Returns (list of output dicts, workspace)."""
+    import torch
+    dtype = torch.float32 if precision == "fp32" else torch.float64
+    device = datas[0]["A"].device
+    batch = len(datas)
+    arr = (LqrProblem * batch)()
+    outs = []
+    for i, data in enumerate(datas):
+        n, m, T = _validate(data, dtype, device)
+        out = outputs[i] if outputs is not None else _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol)
+        outs.append(out)
+        arr[i] = _problem(data, out, 0 if segments is None else segments[i])
+    opts = options(precision, algo)
+    nbytes = lqr_workspace_size(arr, batch, opts)
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    lqr_solve_batched(arr, batch, opts, ws.data_ptr(), ws.numel(), s)
+    return outs, ws

@@ -1,0 +1,308 @@
+// C-ABI entry points: argument validation, the segment planner, workspace
+// carve-out and kernel launches. No device memory is allocated here; every
+// launch goes to the caller's stream and nothing synchronises it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "lqr_kernels.h"
+#include "lqr_layout.h"
+#include "mi355lqr.h"
+
+namespace lqr {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// LDS a gfx950 workgroup may allocate. Plans (segment counts, workspace
+// sizes) are computed against this architectural constant so they do not
+// depend on the machine; launches also check the device's reported limit.
+constexpr size_t kLdsGfx950 = 160 * 1024;
+
+// Largest dynamic LDS allocation a workgroup may ask for on the current device.
+size_t device_lds_bytes() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  size_t bytes = 64 * 1024;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    bytes = (size_t)v;
+  cache[dev] = bytes;
+  return bytes;
+}
+
+// Compute units of an MI355X; the planner sizes segment counts against it.
+constexpr int kComputeUnits = 256;
+
+// Segment count for one instance when the caller leaves it to the planner.
+// Balances the per-segment sweeps (about T/J stages each, run concurrently)
+// against the linking solve (J-1 serially dependent boundary steps), i.e.
+// minimises T/J * c_sweep + J * c_link with c_link/c_sweep ~ 1/4 for the
+// sweep kernels here, giving J ~ 2 sqrt(T); capped so the instances of a
+// batch together do not ask for more than ~2 workgroups per compute unit.
+int plan_segments(int n, int m, int T, int batch, size_t lds_max) {
+  if (sweep_lds(n, m, true) > lds_max || couple_lds(n) > lds_max) return 1;
+  int J = (int)std::lround(2.0 * std::sqrt((double)T));
+  const int cap = std::max(1, 2 * kComputeUnits / std::max(1, batch));
+  J = std::min(J, cap);
+  return std::max(1, std::min(J, T));
+}
+
+struct InstPlan {
+  int J;
+  size_t ws_off;   // bytes from the workspace base
+  size_t ws_bytes;
+};
+
+struct BatchPlan {
+  std::vector<InstPlan> inst;
+  size_t table_bytes = 0;  // descriptor table + work items, at the workspace base
+  size_t total_bytes = 0;
+  int nitems = 0;
+  size_t lds1 = 0, lds2 = 0, lds3 = 0, lds_serial = 0;
+};
+
+bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL; }
+
+lqr_status_t check_options(const lqr_options_t* o) {
+  if (!o) return LQR_SUCCESS;
+  if (o->flags != 0) return LQR_ERR_INVALID_ARG;
+  if (o->algo != LQR_ALGO_PARALLEL && o->algo != LQR_ALGO_SERIAL) return LQR_ERR_INVALID_ARG;
+  if (o->precision != LQR_PREC_FP64 && o->precision != LQR_PREC_MIXED &&
+      o->precision != LQR_PREC_FP32)
+    return LQR_ERR_INVALID_ARG;
+  if (o->precision != LQR_PREC_FP64) return LQR_ERR_UNSUPPORTED;
+  return LQR_SUCCESS;
+}
+
+lqr_status_t check_dims(const lqr_problem_t& p) {
+  if (p.n < 1 || p.m < 1 || p.T < 1) return LQR_ERR_INVALID_ARG;
+  if (p.segments < 0 || p.segments > p.T) return LQR_ERR_INVALID_ARG;
+  return LQR_SUCCESS;
+}
+
+lqr_status_t check_pointers(const lqr_problem_t& p) {
+  if (!p.A || !p.B || !p.c || !p.Q || !p.q || !p.R || !p.r || !p.x0) return LQR_ERR_INVALID_ARG;
+  if (!p.K || !p.k || !p.x || !p.u || !p.info) return LQR_ERR_INVALID_ARG;
+  if (p.lam && (!p.P || !p.p)) return LQR_ERR_INVALID_ARG;
+  return LQR_SUCCESS;
+}
+
+lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
+                       BatchPlan* plan) {
+  if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
+  lqr_status_t st = check_options(opts);
+  if (st != LQR_SUCCESS) return st;
+  const size_t lds_max = kLdsGfx950;
+  const bool serial = is_serial(opts);
+  plan->inst.resize(batch);
+  int items = 0;
+  for (int i = 0; i < batch; ++i) {
+    const lqr_problem_t& p = probs[i];
+    if ((st = check_dims(p)) != LQR_SUCCESS) return st;
+    int J = serial ? 1 : (p.segments > 0 ? p.segments : plan_segments(p.n, p.m, p.T, batch, lds_max));
+    const size_t plain = sweep_lds(p.n, p.m, false);
+    if (plain > lds_max) return LQR_ERR_UNSUPPORTED;
+    if (J > 1 && (sweep_lds(p.n, p.m, true) > lds_max || couple_lds(p.n) > lds_max))
+      return LQR_ERR_UNSUPPORTED;
+    plan->inst[i].J = J;
+    items += J;
+    plan->lds_serial = std::max(plan->lds_serial, std::max(plain, rollout_lds(p.n, p.m)));
+    plan->lds1 = std::max(plan->lds1, J > 1 ? sweep_lds(p.n, p.m, true) : plain);
+    plan->lds2 = std::max(plan->lds2, couple_lds(p.n));
+    plan->lds3 = std::max(plan->lds3, std::max(plain, rollout_lds(p.n, p.m)));
+  }
+  plan->nitems = items;
+  plan->table_bytes = align_up(sizeof(InstDesc) * (size_t)batch) + align_up(sizeof(WorkItem) * (size_t)items);
+  size_t off = plan->table_bytes;
+  for (int i = 0; i < batch; ++i) {
+    const lqr_problem_t& p = probs[i];
+    const int J = plan->inst[i].J;
+    const size_t bytes = align_up(ws_doubles(p.n, J) * sizeof(double)) + align_up(sizeof(int32_t) * J);
+    plan->inst[i].ws_off = off;
+    plan->inst[i].ws_bytes = bytes;
+    off += bytes;
+  }
+  plan->total_bytes = off;
+  return LQR_SUCCESS;
+}
+
+lqr_status_t check_device(const BatchPlan& plan) {
+  const size_t lim = device_lds_bytes();
+  const size_t need = std::max(std::max(plan.lds1, plan.lds2), std::max(plan.lds3, plan.lds_serial));
+  return need <= lim ? LQR_SUCCESS : LQR_ERR_UNSUPPORTED;
+}
+
+InstDesc make_desc(const lqr_problem_t& p, int J, char* ws_base, size_t ws_off) {
+  InstDesc d;
+  d.n = p.n;
+  d.m = p.m;
+  d.T = p.T;
+  d.J = J;
+  d.A = static_cast<const double*>(p.A);
+  d.B = static_cast<const double*>(p.B);
+  d.c = static_cast<const double*>(p.c);
+  d.Q = static_cast<const double*>(p.Q);
+  d.q = static_cast<const double*>(p.q);
+  d.R = static_cast<const double*>(p.R);
+  d.r = static_cast<const double*>(p.r);
+  d.S = static_cast<const double*>(p.S);
+  d.x0 = static_cast<const double*>(p.x0);
+  d.K = static_cast<double*>(p.K);
+  d.k = static_cast<double*>(p.k);
+  d.P = static_cast<double*>(p.P);
+  d.p = static_cast<double*>(p.p);
+  d.x = static_cast<double*>(p.x);
+  d.u = static_cast<double*>(p.u);
+  d.lam = static_cast<double*>(p.lam);
+  d.chol = static_cast<double*>(p.chol);
+  d.info = p.info;
+  d.ws = reinterpret_cast<double*>(ws_base + ws_off);
+  d.fail = reinterpret_cast<int32_t*>(ws_base + ws_off + align_up(ws_doubles(p.n, J) * sizeof(double)));
+  return d;
+}
+
+// Host copies of uploaded batched plans, keyed by workspace address, so that
+// a call under stream capture can verify that the plan it needs is resident.
+std::mutex g_plan_mu;
+std::map<void*, std::vector<char>> g_plans;
+
+}  // namespace
+}  // namespace lqr
+
+using namespace lqr;
+
+extern "C" {
+
+const char* lqr_status_string(lqr_status_t s) {
+  switch (s) {
+    case LQR_SUCCESS: return "success";
+    case LQR_ERR_INVALID_ARG: return "invalid argument";
+    case LQR_ERR_NOT_PD: return "input Hessian not positive definite";
+    case LQR_ERR_SINGULAR_COUPLING: return "singular linking system";
+    case LQR_ERR_NONFINITE: return "non-finite value";
+    case LQR_ERR_WORKSPACE: return "workspace missing or too small";
+    case LQR_ERR_HIP: return "HIP runtime error";
+    case LQR_ERR_UNSUPPORTED: return "unsupported size or mode";
+  }
+  return "unknown status";
+}
+
+lqr_status_t lqr_workspace_size(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
+                                size_t* bytes) {
+  try {
+    if (!bytes) return LQR_ERR_INVALID_ARG;
+    BatchPlan plan;
+    lqr_status_t st = make_plan(probs, batch, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    *bytes = plan.total_bytes;
+    return LQR_SUCCESS;
+  } catch (const std::bad_alloc&) {
+    return LQR_ERR_INVALID_ARG;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
+lqr_status_t lqr_solve(const lqr_problem_t* prob, const lqr_options_t* opts, void* ws,
+                       size_t ws_bytes, void* stream) {
+  try {
+    BatchPlan plan;
+    lqr_status_t st = make_plan(prob, 1, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    if ((st = check_pointers(*prob)) != LQR_SUCCESS) return st;
+    if ((st = check_device(plan)) != LQR_SUCCESS) return st;
+    if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+    const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = is_serial(opts) ? launch_serial(d, plan.lds_serial, s)
+                                   : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, s);
+    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
+lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
+                               void* ws, size_t ws_bytes, void* stream) {
+  try {
+    BatchPlan plan;
+    lqr_status_t st = make_plan(probs, batch, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    for (int i = 0; i < batch; ++i)
+      if ((st = check_pointers(probs[i])) != LQR_SUCCESS) return st;
+    if ((st = check_device(plan)) != LQR_SUCCESS) return st;
+    if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+    char* base = static_cast<char*>(ws);
+    const bool serial = is_serial(opts);
+
+    // Host image of the table: descriptors, then (instance, segment) items
+    // ordered with the longest segments first.
+    std::vector<char> table(plan.table_bytes, 0);
+    InstDesc* descs = reinterpret_cast<InstDesc*>(table.data());
+    WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + align_up(sizeof(InstDesc) * batch));
+    std::vector<std::pair<double, WorkItem>> order;
+    order.reserve(plan.nitems);
+    for (int i = 0; i < batch; ++i) {
+      descs[i] = make_desc(probs[i], plan.inst[i].J, base, plan.inst[i].ws_off);
+      const lqr_problem_t& p = probs[i];
+      const int J = plan.inst[i].J;
+      for (int j = 0; j < J; ++j) {
+        const int len = seg_begin(p.T, J, j + 1) - seg_begin(p.T, J, j);
+        const double cost = (double)len * (double)p.n * p.n * (p.n + p.m);
+        order.push_back({cost, WorkItem{i, j}});
+      }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, WorkItem>& a, const std::pair<double, WorkItem>& b) {
+                       return a.first > b.first;
+                     });
+    for (int i = 0; i < plan.nitems; ++i) items[i] = order[i].second;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
+    {
+      std::lock_guard<std::mutex> lock(g_plan_mu);
+      if (cap != hipStreamCaptureStatusNone) {
+        auto it = g_plans.find(ws);
+        if (it == g_plans.end() || it->second != table) return LQR_ERR_INVALID_ARG;
+      } else {
+        std::vector<char>& keep = g_plans[ws];
+        keep = table;
+        if (hipMemcpyAsync(ws, keep.data(), keep.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+          return LQR_ERR_HIP;
+      }
+    }
+    const InstDesc* ddesc = reinterpret_cast<const InstDesc*>(base);
+    const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + align_up(sizeof(InstDesc) * batch));
+    hipError_t e = serial ? launch_serial_batched(ddesc, batch, plan.lds_serial, s)
+                          : launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.lds1,
+                                                    plan.lds2, plan.lds3, s);
+    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
+lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_grad_t* grads,
+                          const lqr_options_t* opts, void* ws, size_t ws_bytes, void* stream) {
+  (void)probs; (void)batch; (void)grads; (void)opts; (void)ws; (void)ws_bytes; (void)stream;
+  return LQR_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

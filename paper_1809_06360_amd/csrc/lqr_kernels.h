@@ -1,0 +1,23 @@
+// Host-side launchers of the solver kernels (defined in lqr_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lqr_layout.h"
+#include "mi355lqr.h"
+
+namespace lqr {
+
+// Single instance, J = d.J segments: phase 1 (J workgroups), phase 2 (one),
+// phase 3 (J workgroups); ldsN = dynamic LDS bytes of each launch.
+hipError_t launch_parallel(const InstDesc& d, size_t lds1, size_t lds2, size_t lds3,
+                           hipStream_t stream);
+// Single instance, one plain recursion over the whole horizon.
+hipError_t launch_serial(const InstDesc& d, size_t lds, hipStream_t stream);
+// Batched forms: descriptors and work items live in device memory.
+hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items, int nitems,
+                                   int ninst, size_t lds1, size_t lds2, size_t lds3,
+                                   hipStream_t stream);
+hipError_t launch_serial_batched(const InstDesc* descs, int ninst, size_t lds, hipStream_t stream);
+
+}  // namespace lqr

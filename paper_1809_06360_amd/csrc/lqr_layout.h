@@ -1,0 +1,88 @@
+// Shapes shared by the host planner and the kernels: the per-instance device
+// descriptor, segment boundaries, workspace strides and LDS footprints.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define LQR_HD __host__ __device__ inline
+#else
+#define LQR_HD inline
+#endif
+
+namespace lqr {
+
+// One instance as the kernels see it (FP64 element type). Built on the host
+// from lqr_problem_t plus the workspace carve-out; passed by value to the
+// single-instance kernels and stored in a device table for batched launches.
+struct InstDesc {
+  int32_t n, m, T, J;
+  const double *A, *B, *c, *Q, *q, *R, *r, *S, *x0;
+  double *K, *k, *P, *p, *x, *u, *lam, *chol;
+  int32_t *info;
+  double *ws;      // per-instance scratch (segment summaries, boundary values, link maps)
+  int32_t *fail;   // [J] first failing stage + 1 seen by each segment's sweep, 0 if none
+};
+
+// A unit of batched work: instance index and segment index.
+struct WorkItem {
+  int32_t inst, seg;
+};
+
+// Segment j covers stages [seg_begin(j), seg_begin(j+1)); the first T mod J
+// segments are one stage longer.
+LQR_HD int seg_begin(int T, int J, int j) {
+  const int L = T / J, extra = T % J;
+  return j * L + (j < extra ? j : extra);
+}
+
+// Workspace strides, in doubles.
+//  seg[j], j < J-1 : P0 (n*n) | Gamma (n*n) | Psi (n*n) | pbar (n) | psi (n)
+//  bnd[j], j < J   : P (n*n) | p (n) | x (n)           value and state at seg_begin(j)
+//  link[j], j < J-1: F (n*n) | f (n)                   x_{t_{j+1}} = F x_{t_j} + f
+LQR_HD size_t seg_stride(int n) { return 3 * (size_t)n * n + 2 * (size_t)n; }
+LQR_HD size_t bnd_stride(int n) { return (size_t)n * n + 2 * (size_t)n; }
+LQR_HD size_t link_stride(int n) { return (size_t)n * n + (size_t)n; }
+
+LQR_HD size_t ws_doubles(int n, int J) {
+  return (size_t)(J - 1) * seg_stride(n) + (size_t)J * bnd_stride(n) +
+         (size_t)(J - 1) * link_stride(n);
+}
+LQR_HD double* ws_seg(double* ws, int n, int j) { return ws + (size_t)j * seg_stride(n); }
+LQR_HD double* ws_bnd(double* ws, int n, int J, int j) {
+  return ws + (size_t)(J - 1) * seg_stride(n) + (size_t)j * bnd_stride(n);
+}
+LQR_HD double* ws_link(double* ws, int n, int J, int j) {
+  return ws + (size_t)(J - 1) * seg_stride(n) + (size_t)J * bnd_stride(n) +
+         (size_t)j * link_stride(n);
+}
+
+// LDS footprints in bytes (FP64). The sweep keeps, per workgroup:
+//  sP  n x n           value Hessian of the next stage
+//  sp  n               value gradient
+//  sX  n x (m+n+1)     [B_t | A_t | c_t]
+//  sY  n x W           [P B | P A | P c + p | Gamma]          (Gamma: dual sweep only)
+//  sG  m x W           [R + B'PB | S + B'PA | r + B'(Pc+p) | B'Gamma]
+//  dual only: sPsi n x n, spsi n, sgc n
+//  sd  m pivots, flags
+// with W = m + n + 1 (+ n for the dual sweep).
+LQR_HD int sweep_w(int n, int m, bool dual) { return m + n + 1 + (dual ? n : 0); }
+
+LQR_HD size_t sweep_lds(int n, int m, bool dual) {
+  const size_t W = (size_t)sweep_w(n, m, dual);
+  size_t dbl = (size_t)n * n + n + (size_t)n * (m + n + 1) + (size_t)n * W + (size_t)m * W + m;
+  if (dual) dbl += (size_t)n * n + 2 * (size_t)n;
+  return dbl * 8 + 64;
+}
+
+// Linking solve: sPn n x n, spn n, sA1 n x n, sN n x (2n+1), vectors, pivots.
+LQR_HD size_t couple_lds(int n) {
+  const size_t dbl = 2 * (size_t)n * n + (size_t)n * (2 * n + 1) + 6 * (size_t)n;
+  return dbl * 8 + 2 * (size_t)n * 4 + 64;
+}
+
+// Forward simulation: x_t and x_{t+1} (n each), u_t (m).
+LQR_HD size_t rollout_lds(int n, int m) { return (2 * (size_t)n + m) * 8 + 64; }
+
+}  // namespace lqr

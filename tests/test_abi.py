@@ -1,0 +1,125 @@
+"""The C-ABI library loads and exports what include/mi355lqr.h declares (no GPU).
+
+Also checks that the ctypes mirror of every struct has the C layout (a tiny C
+program compiled with gcc prints sizeof/offsetof from the header), and the
+host-side argument validation of the entry points, none of which launches a
+kernel.
+"""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1809_06360_amd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355lqr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lqr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.library()
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    fields = {"lqr_problem_t": L.LqrProblem, "lqr_options_t": L.LqrOptions, "lqr_grad_t": L.LqrGrad}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mi355lqr.h"', 'int main(void) {']
+    for cname, py in fields.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, py in fields.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_status_strings():
+    for code in range(8):
+        assert L.lqr_status_string(code)
+    assert L.lqr_status_string(0) == "success"
+
+
+def _prob(n=4, m=2, T=8, J=0):
+    return L.LqrProblem(n, m, T, J)
+
+
+@pytest.mark.parametrize("n,m,T,J", [(0, 1, 4, 0), (2, 0, 4, 0), (2, 1, 0, 0), (2, 1, 4, 5), (2, 1, 4, -1)])
+def test_workspace_size_rejects_bad_dimensions(n, m, T, J):
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, J)), 1, L.options())
+    assert e.value.status == L.ERR_INVALID_ARG
+
+
+def test_workspace_size_rejects_bad_options():
+    opts = L.options()
+    opts.flags = 1
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(ctypes.byref(_prob()), 1, opts)
+    assert e.value.status == L.ERR_INVALID_ARG
+    with pytest.raises(L.LQRError):
+        L.lqr_workspace_size(ctypes.byref(_prob()), 0, L.options())
+
+
+def test_workspace_size_is_machine_independent_and_monotone():
+    a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options())
+    b = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 0)), 1, L.options())
+    c = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 16)), 1, L.options())
+    assert a == b     # the planner picks 64 segments for T = 1024
+    assert c < a
+    arr = (L.LqrProblem * 2)(_prob(8, 4, 64, 4), _prob(12, 3, 50, 7))
+    both = L.lqr_workspace_size(arr, 2, L.options())
+    assert both > L.lqr_workspace_size(ctypes.byref(arr[1]), 1, L.options())
+
+
+def test_solve_rejects_null_pointers_and_small_workspace():
+    prob = _prob(4, 2, 8, 2)
+    with pytest.raises(L.LQRError) as e:     # all data pointers NULL
+        L.lqr_solve(prob, L.options(), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    for name in ("A", "B", "c", "Q", "q", "R", "r", "x0", "K", "k", "x", "u", "info"):
+        setattr(prob, name, 256)
+    prob.lam = 256        # the costate needs P and p
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_solve(prob, L.options(), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    prob.lam = None
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_solve(prob, L.options(), 256, 16, 0)
+    assert e.value.status == L.ERR_WORKSPACE
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_solve(prob, L.options(), None, 1 << 20, 0)
+    assert e.value.status == L.ERR_WORKSPACE
+
+
+def test_oversized_problem_is_unsupported_not_crashing():
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(ctypes.byref(_prob(200, 100, 16, 0)), 1, L.options())
+    assert e.value.status == L.ERR_UNSUPPORTED

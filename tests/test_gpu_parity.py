@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every case feeds the same seeded FP64 inputs to both sides and compares every
+output (K, k, P, p, x, u, costate) element by element in relative Frobenius
+norm; FP64 tolerance 1e-9. Sizes span several 4x4 register tiles with ragged
+edges, segment counts that do not divide the horizon, one-stage segments
+(J = T) and a single segment (J = 1), and the two workloads the benchmark and
+the small demo use at full size.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import FP64_TOL, compare, host, to_device
+from synthetic import WORKLOADS, make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _solve(prob, **kw):
+    import paper_1809_06360_amd as L
+    out = L.solve(to_device(prob), **kw)
+    torch.cuda.synchronize()
+    return host(out)
+
+
+RAGGED = [
+    # (cfg, n, m, T, J, cross)
+    (10, 20, 7, 50, 7, False),
+    (11, 5, 3, 13, 13, True),     # one stage per segment
+    (12, 9, 9, 40, 1, False),     # single segment
+    (13, 1, 1, 10, 3, False),
+    (14, 33, 17, 70, 9, True),
+    (15, 17, 5, 37, 36, False),   # one segment of two stages, the rest of one
+    (16, 48, 24, 96, 6, False),
+    (17, 3, 6, 25, 4, True),      # more inputs than states
+]
+
+
+@pytest.mark.parametrize("cfg,n,m,T,J,cross", RAGGED)
+@pytest.mark.parametrize("algo", ["parallel", "serial"])
+def test_ragged_sizes_match_oracle(cfg, n, m, T, J, cross, algo):
+    prob = make_instance(cfg, 0, n, m, T, cross_term=cross)
+    ref = oracle.solve(prob)
+    got = _solve(prob, segments=J, algo=algo)
+    assert int(got["info"][0]) == 0
+    compare(got, ref, label="%s n=%d m=%d T=%d J=%d" % (algo, n, m, T, J))
+
+
+@pytest.mark.parametrize("key", ["small", "large"])
+@pytest.mark.parametrize("algo", ["parallel", "serial"])
+def test_named_workloads_match_oracle(key, algo):
+    w = WORKLOADS[key]
+    (n, m, T), = w.dims
+    prob = make_instance(w.cfg, 0, n, m, T)
+    ref = oracle.solve(prob)
+    got = _solve(prob, segments=w.segments, algo=algo)
+    assert int(got["info"][0]) == 0
+    errs = compare(got, ref, label=w.name)
+    print(w.name, algo, {k: "%.2e" % v for k, v in errs.items()})
+
+
+def test_single_segment_equals_serial_kernel_bitwise():
+    prob = make_instance(20, 0, 12, 5, 30)
+    a = _solve(prob, segments=1, algo="parallel")
+    b = _solve(prob, algo="serial")
+    for k in ("K", "k", "P", "p", "x", "u", "lam"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_runs_are_bitwise_deterministic():
+    prob = make_instance(21, 0, 16, 8, 64)
+    a = _solve(prob, segments=8)
+    b = _solve(prob, segments=8)
+    for k in ("K", "k", "P", "p", "x", "u"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_cholesky_factor_output():
+    prob = make_instance(22, 0, 6, 4, 12)
+    got = _solve(prob, segments=3, with_chol=True)
+    ref = oracle.solve(prob)
+    P = ref["P"]
+    for t in range(12):
+        H = prob["R"][t] + prob["B"][t].T @ P[t + 1] @ prob["B"][t]
+        L = got["chol"][t]
+        assert np.allclose(np.triu(L, 1), 0.0)
+        assert np.linalg.norm(L @ L.T - H) <= 1e-11 * np.linalg.norm(H)
+
+
+@pytest.mark.parametrize("algo,J", [("serial", 1), ("parallel", 1), ("parallel", 3), ("parallel", 10)])
+def test_indefinite_input_hessian_is_reported(algo, J):
+    prob = make_instance(23, 0, 4, 2, 10)
+    prob["R"][6] = -50.0 * np.eye(2)
+    assert oracle.solve(prob)["info"] == 7
+    got = _solve(prob, segments=J, algo=algo)
+    assert int(got["info"][0]) == 7
+
+
+def test_outputs_not_requested_are_not_needed():
+    import paper_1809_06360_amd as L
+    prob = make_instance(24, 0, 10, 4, 40)
+    out = L.solve(to_device(prob), segments=5, with_P=False, with_lam=False)
+    torch.cuda.synchronize()
+    ref = oracle.solve(prob)
+    compare(host(out), ref, keys=("K", "k", "x", "u"))
+    assert "P" not in out
+
+
+def test_batched_uneven_matches_oracle_and_single_calls():
+    import paper_1809_06360_amd as L
+    dims = [(4, 2, 64, 4), (20, 7, 50, 0), (33, 17, 70, 9), (1, 1, 5, 0), (48, 24, 128, 8), (9, 9, 40, 1)]
+    probs = [make_instance(30, i, n, m, T) for i, (n, m, T, _) in enumerate(dims)]
+    outs, _ = L.solve_batched([to_device(p) for p in probs], segments=[d[3] for d in dims])
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        got = host(outs[i])
+        assert int(got["info"][0]) == 0
+        compare(got, oracle.solve(p), label="instance %d %s" % (i, dims[i]))
+        if dims[i][3] > 0:
+            single = _solve(p, segments=dims[i][3])
+            for k in ("K", "k", "P", "p", "x", "u"):
+                assert np.array_equal(got[k], single[k]), (i, k)
+
+
+def test_batched_workload_sample_matches_oracle():
+    """The 256-instance uneven batch at full size, solved in one call; every
+    instance is checked for finiteness and a fixed sample of 24 against the
+    oracle."""
+    import paper_1809_06360_amd as L
+    w = WORKLOADS["batched"]
+    probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
+    outs, _ = L.solve_batched([to_device(p) for p in probs])
+    torch.cuda.synchronize()
+    for i in range(w.batch):
+        assert int(outs[i]["info"][0]) == 0
+        assert torch.isfinite(outs[i]["x"]).all()
+    rng = np.random.default_rng(5)
+    for i in sorted(rng.choice(w.batch, size=24, replace=False)):
+        compare(host(outs[i]), oracle.solve(probs[i]), label="batched instance %d %s" % (i, w.dims[i]))

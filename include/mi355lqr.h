@@ -141,6 +141,15 @@ lqr_status_t lqr_workspace_size(const lqr_problem_t *probs, int32_t batch,
 lqr_status_t lqr_solve(const lqr_problem_t *prob, const lqr_options_t *opts,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* Run one launch of lqr_solve's sequence: phase 1 (segment sweeps), 2
+ * (linking solve) or 3 (rebuild and forward simulation). Calling phases 1, 2,
+ * 3 in order on one stream with the same arguments and workspace is exactly
+ * lqr_solve; this exists so that callers can time or interleave the phases.
+ * With LQR_ALGO_SERIAL, phase 1 is the whole solve and phases 2, 3 do nothing.
+ * Returns LQR_ERR_INVALID_ARG for a phase outside 1..3. */
+lqr_status_t lqr_solve_phase(const lqr_problem_t *prob, const lqr_options_t *opts, int32_t phase,
+                             void *ws, size_t ws_bytes, void *stream);
+
 /* Solve `batch` independent instances of possibly different n, m, T in one
  * launch sequence. The execution plan (per-instance segment counts and the
  * work-item table) is built on the host and copied into the workspace; when a

@@ -17,7 +17,7 @@ import os
 
 __all__ = [
     "LIB_PATH", "library", "LqrProblem", "LqrOptions", "LqrGrad",
-    "lqr_workspace_size", "lqr_solve", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
+    "lqr_workspace_size", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
     "solve", "solve_batched", "LQRError",
     "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
     "INFO_COUPLING",
@@ -50,7 +50,7 @@ class LqrGrad(ctypes.Structure):
                                          "dR", "dr", "dS", "dx0")]
 
 
-EXPORTS = ("lqr_workspace_size", "lqr_solve", "lqr_solve_batched", "lqr_backward",
+EXPORTS = ("lqr_workspace_size", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward",
            "lqr_status_string")
 
 _lib = None
@@ -75,6 +75,8 @@ def library():
         lib.lqr_workspace_size.restype = ctypes.c_int
         lib.lqr_solve.argtypes = [P(LqrProblem), P(LqrOptions), _vp, ctypes.c_size_t, _vp]
         lib.lqr_solve.restype = ctypes.c_int
+        lib.lqr_solve_phase.argtypes = [P(LqrProblem), P(LqrOptions), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+        lib.lqr_solve_phase.restype = ctypes.c_int
         lib.lqr_solve_batched.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), _vp,
                                           ctypes.c_size_t, _vp]
         lib.lqr_solve_batched.restype = ctypes.c_int
@@ -106,6 +108,13 @@ def lqr_solve(prob: LqrProblem, opts: LqrOptions, ws: int, ws_bytes: int, stream
     st = library().lqr_solve(ctypes.byref(prob), ctypes.byref(opts), ws, ws_bytes, stream)
     if st != SUCCESS:
         raise LQRError(st, "lqr_solve")
+
+
+def lqr_solve_phase(prob: LqrProblem, opts: LqrOptions, phase: int, ws: int, ws_bytes: int,
+                    stream: int) -> None:
+    st = library().lqr_solve_phase(ctypes.byref(prob), ctypes.byref(opts), int(phase), ws, ws_bytes, stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_solve_phase")
 
 
 def lqr_solve_batched(probs, batch: int, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:

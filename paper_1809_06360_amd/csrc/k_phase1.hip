@@ -1,0 +1,36 @@
+// Phase 1: parametric (dual) sweep of every segment but the last; plain
+// recursion of the last segment.
+#include "lqr_device.h"
+#include "lqr_launch.h"
+
+namespace lqr {
+
+// Instantiated per register width MW (8..64, the padded input dimension m held in
+// registers by the elimination) and per product engine MF (matrix cores for
+// n >= 32), so that each launch runs one compact variant.
+template <int MW, bool MF>
+__global__ __launch_bounds__(kThreads) void k_phase1(InstDesc single, const InstDesc* descs,
+                                                     const WorkItem* items) {
+  extern __shared__ double smem[];
+  InstDesc d;
+  int seg;
+  select_item(single, descs, items, d, seg);
+  phase1_item<MW, MF>(d, seg, smem);
+}
+
+template <int W, bool M>
+struct k_phase1_ref {
+  static auto fn() { return &k_phase1<W, M>; }
+};
+
+hipError_t launch_k_phase1(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                   unsigned grid, int width, bool mf, size_t lds, hipStream_t stream) {
+  return with_variant<k_phase1_ref>(width, mf, [&](auto k) -> hipError_t {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, stream, single, descs, items);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace lqr

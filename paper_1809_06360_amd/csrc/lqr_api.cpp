@@ -52,8 +52,11 @@ constexpr int kComputeUnits = 256;
 // minimises T/J * c_sweep + J * c_link with c_link/c_sweep ~ 1/4 for the
 // sweep kernels here, giving J ~ 2 sqrt(T); capped so the instances of a
 // batch together do not ask for more than ~2 workgroups per compute unit.
-int plan_segments(int n, int m, int T, int batch, size_t lds_max) {
-  if (sweep_lds(n, m, true) > lds_max || couple_lds(n) > lds_max) return 1;
+int plan_segments(int n, int m, int T, int batch, size_t lds_max, int mw, int nw) {
+  if (sweep_lds(n, m, true, mw) > lds_max || couple_lds(n, nw) > lds_max ||
+      !sweep_fits_regs(n, m, true) ||
+      n > 64)
+    return 1;
   int J = (int)std::lround(2.0 * std::sqrt((double)T));
   const int cap = std::max(1, 2 * kComputeUnits / std::max(1, batch));
   J = std::min(J, cap);
@@ -71,6 +74,7 @@ struct BatchPlan {
   size_t table_bytes = 0;  // descriptor table + work items, at the workspace base
   size_t total_bytes = 0;
   int nitems = 0;
+  int max_n = 1, max_m = 1;
   size_t lds1 = 0, lds2 = 0, lds3 = 0, lds_serial = 0;
 };
 
@@ -109,19 +113,34 @@ lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_
   const bool serial = is_serial(opts);
   plan->inst.resize(batch);
   int items = 0;
+  // The batch's largest dimensions pick the kernel variants, whose register
+  // widths fix the LDS layouts; segment counts are planned against them.
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
     if ((st = check_dims(p)) != LQR_SUCCESS) return st;
-    int J = serial ? 1 : (p.segments > 0 ? p.segments : plan_segments(p.n, p.m, p.T, batch, lds_max));
-    const size_t plain = sweep_lds(p.n, p.m, false);
-    if (plain > lds_max) return LQR_ERR_UNSUPPORTED;
-    if (J > 1 && (sweep_lds(p.n, p.m, true) > lds_max || couple_lds(p.n) > lds_max))
-      return LQR_ERR_UNSUPPORTED;
+    plan->max_n = std::max(plan->max_n, p.n);
+    plan->max_m = std::max(plan->max_m, p.m);
+  }
+  const int mw = pad_rows(plan->max_m), nw = pad_rows(plan->max_n);
+  for (int i = 0; i < batch; ++i) {
+    const lqr_problem_t& p = probs[i];
+    const int J = serial ? 1
+                         : (p.segments > 0 ? p.segments
+                                           : plan_segments(p.n, p.m, p.T, batch, lds_max, mw, nw));
     plan->inst[i].J = J;
     items += J;
+  }
+  for (int i = 0; i < batch; ++i) {
+    const lqr_problem_t& p = probs[i];
+    const int J = plan->inst[i].J;
+    const size_t plain = sweep_lds(p.n, p.m, false, mw);
+    if (plain > lds_max || !sweep_fits_regs(p.n, p.m, false)) return LQR_ERR_UNSUPPORTED;
+    if (J > 1 && (sweep_lds(p.n, p.m, true, mw) > lds_max || couple_lds(p.n, nw) > lds_max ||
+                  !sweep_fits_regs(p.n, p.m, true) || p.n > 64 || 2 * p.n + 1 > 256))
+      return LQR_ERR_UNSUPPORTED;
     plan->lds_serial = std::max(plan->lds_serial, std::max(plain, rollout_lds(p.n, p.m)));
-    plan->lds1 = std::max(plan->lds1, J > 1 ? sweep_lds(p.n, p.m, true) : plain);
-    plan->lds2 = std::max(plan->lds2, couple_lds(p.n));
+    plan->lds1 = std::max(plan->lds1, J > 1 ? sweep_lds(p.n, p.m, true, mw) : plain);
+    plan->lds2 = std::max(plan->lds2, couple_lds(p.n, nw));
     plan->lds3 = std::max(plan->lds3, std::max(plain, rollout_lds(p.n, p.m)));
   }
   plan->nitems = items;
@@ -236,6 +255,32 @@ lqr_status_t lqr_solve(const lqr_problem_t* prob, const lqr_options_t* opts, voi
   }
 }
 
+lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opts, int32_t phase,
+                             void* ws, size_t ws_bytes, void* stream) {
+  try {
+    if (phase < 1 || phase > 3) return LQR_ERR_INVALID_ARG;
+    BatchPlan plan;
+    lqr_status_t st = make_plan(prob, 1, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    if ((st = check_pointers(*prob)) != LQR_SUCCESS) return st;
+    if ((st = check_device(plan)) != LQR_SUCCESS) return st;
+    if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+    const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (is_serial(opts)) {
+      if (phase == 1) e = launch_serial(d, plan.lds_serial, s);
+    } else {
+      const size_t lds = phase == 1 ? plan.lds1 : phase == 2 ? plan.lds2 : plan.lds3;
+      e = launch_phase(d, phase, lds, s);
+    }
+    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
 lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
                                void* ws, size_t ws_bytes, void* stream) {
   try {
@@ -290,9 +335,10 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     }
     const InstDesc* ddesc = reinterpret_cast<const InstDesc*>(base);
     const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + align_up(sizeof(InstDesc) * batch));
-    hipError_t e = serial ? launch_serial_batched(ddesc, batch, plan.lds_serial, s)
-                          : launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.lds1,
-                                                    plan.lds2, plan.lds3, s);
+    hipError_t e = serial ? launch_serial_batched(ddesc, batch, plan.max_n, plan.max_m,
+                                                  plan.lds_serial, s)
+                          : launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n,
+                                                    plan.max_m, plan.lds1, plan.lds2, plan.lds3, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;

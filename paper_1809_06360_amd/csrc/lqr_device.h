@@ -1,4 +1,4 @@
-// Kernels of the parallel Riccati recursion (FP64), gfx950.
+// Device code of the parallel Riccati recursion (FP64), gfx950.
 //
 // The horizon [0, T) is cut into J segments (Sec. II-A: dividing into
 // sub-trajectories). The three launches are
@@ -20,23 +20,27 @@
 //            link point (eq. xopt/uopt evaluated at the link points).
 // The serial kernel runs the plain recursion over the whole horizon in one
 // workgroup and is the GPU baseline.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
-#include "lqr_kernels.h"
 #include "lqr_layout.h"
+#include "mi355lqr.h"
 #include "wg_linalg.h"
 
 namespace lqr {
 
-namespace {
 
+// LDS of one sweep. G (input Hessian and right-hand sides) is column-major
+// with leading dimension mp = MW + 1 (MW the kernel's register width, >= m):
+// element (i, j) at G[j * mp + i].
 struct SweepLds {
-  double *P, *p, *X, *Y, *G, *d, *Psi, *psi, *gc;
+  double *P, *p, *X, *Y, *G, *E, *Psi, *psi, *gc;
   int* bad;
-  int WX, W;
+  int WX, W, mp;
 };
 
-LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual) {
+LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual, int mw) {
   SweepLds s;
   s.WX = m + n + 1;
   s.W = sweep_w(n, m, dual);
@@ -45,8 +49,9 @@ LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual) {
   s.p = q; q += n;
   s.X = q; q += n * s.WX;
   s.Y = q; q += n * s.W;
-  s.G = q; q += m * s.W;
-  s.d = q; q += m;
+  s.mp = mw + 1;
+  s.G = q; q += s.mp * s.W;
+  s.E = q; q += 3 * mw;
   s.Psi = s.psi = s.gc = nullptr;
   if (dual) {
     s.Psi = q; q += n * n;
@@ -67,45 +72,50 @@ LQR_DEV void load_stage(const InstDesc& d, int t, const SweepLds& s) {
 }
 
 // Y[:, 0:WX] = P [B | A | c] + [0 | 0 | p]
+template <int MM, bool MF>
 LQR_DEV void stage_products(const InstDesc& d, const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX, W = s.W;
   double* Y = s.Y;
   const double* p = s.p;
-  gemm<4, 4, false, false>(n, WX, n, s.P, n, s.X, WX, [=](int i, int j, double v) {
-    if (j == m + n) v += p[i];
-    Y[i * W + j] = v;
-  });
+  pgemm_sub<MF, false, false, false, false>(n, WX, n, s.P, n, s.X, WX, 0, s.P, n, s.X, WX,
+                                        [=](int i, int j, double v) {
+                                          if (j == m + n) v += p[i];
+                                          Y[i * W + j] = v;
+                                        });
 }
 
 // G[:, 0:ncols] = B' Y[:, 0:ncols] + [R_t | S_t | r_t | 0]
+template <int MM, bool MF>
 LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncols) {
   const int n = d.n, m = d.m, W = s.W;
   const double* Rt = d.R + (size_t)t * m * m;
   const double* St = d.S ? d.S + (size_t)t * m * n : nullptr;
   const double* rt = d.r + (size_t)t * m;
   double* G = s.G;
-  gemm<4, 4, true, false>(m, ncols, n, s.X, s.WX, s.Y, W, [=](int i, int j, double v) {
-    if (j < m) {
-      v += Rt[i * m + j];
-    } else if (j < m + n) {
-      if (St) v += St[i * n + (j - m)];
-    } else if (j == m + n) {
-      v += rt[i];
-    }
-    G[i * W + j] = v;
-  });
+  const int mp = s.mp;
+  pgemm_sub<MF, true, false, false, false>(m, ncols, n, s.X, s.WX, s.Y, W, 0, s.X, s.WX, s.Y, W,
+                                       [=](int i, int j, double v) {
+                                         if (j < m) {
+                                           v += Rt[i * m + j];
+                                         } else if (j < m + n) {
+                                           if (St) v += St[i * n + (j - m)];
+                                         } else if (j == m + n) {
+                                           v += rt[i];
+                                         }
+                                         G[j * mp + i] = v;
+                                       });
 }
 
 // [P | p] <- [Q_t | q_t] + A'[PA | Pc+p] - Z'[Z | z], lower triangle computed
 // and mirrored; optionally also written to the global outputs Pg, pg.
+template <int MM, bool MF>
 LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg, double* pg) {
   const int n = d.n, m = d.m, W = s.W;
   const double* Qt = d.Q + (size_t)t * n * n;
   const double* qt = d.q + (size_t)t * n;
   double* P = s.P;
   double* p = s.p;
-  gemm_sub<4, 4, true, false, true, false>(
-      n, n + 1, n, s.X + m, s.WX, s.Y + m, W, m, s.G + m, W, s.G + m, W,
+  pgemm_sub<MF, true, false, false, true>(n, n + 1, n, s.X + m, s.WX, s.Y + m, W, m, s.G + m * s.mp, s.mp, s.G + m * s.mp, s.mp,
       [=](int i, int j, double v) {
         if (j < n) {
           if (i >= j) {
@@ -123,16 +133,21 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
           if (pg) pg[i] = v;
         }
       },
-      SkipUpper<4, 4>{n});
+      SkipUpper{n});
 }
 
 // Plain Riccati recursion over stages [t0, t1) from the value (Pend, pend) at
-// stage t1 (global memory). Writes K_t, k_t and, when requested, chol_t, P_t,
-// p_t for t in [t0, t1). Leaves the value at t0 in LDS (s.P, s.p). Returns
-// (largest failing stage) + 1, or 0; uniform across the workgroup.
+// stage t1 (global memory). Per stage, with the Cholesky factor L of the input
+// Hessian H_uu = R + B'PB and Z = L^{-1}[H_ux | h_u] (H_ux = S + B'PA,
+// h_u = r + B'(Pc + p)):
+//   [K | k] = -L^{-T} Z,   P <- Q + A'PA - Z_ux'Z_ux,   p <- q + A'(Pc+p) - Z_ux'z_h.
+// Writes K_t, k_t and, when requested, chol_t, P_t, p_t for t in [t0, t1).
+// Leaves the value at t0 in LDS (s.P, s.p). Returns (largest failing stage)
+// + 1, or 0; uniform across the workgroup.
+template <int MM, bool MF>
 LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, const double* pend,
                         const SweepLds& s) {
-  const int n = d.n, m = d.m, W = s.W, WX = s.WX;
+  const int n = d.n, m = d.m, WX = s.WX;
   if (threadIdx.x == 0) *s.bad = 0;
   load_block(s.P, n, Pend, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) s.p[i] = pend[i];
@@ -140,36 +155,31 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
     __syncthreads();
-    stage_products(d, s);
+    stage_products<MM, MF>(d, s);
     __syncthreads();
-    stage_hessian(d, t, s, WX);
+    stage_hessian<MM, MF>(d, t, s, WX);
     __syncthreads();
-    ldl_forward(s.G, W, m, WX, 0, s.d, s.bad);
+    // L D L' of H_uu with the right-hand sides [H_ux | h_u | I]: Z = L^{-1}[H_ux | h_u]
+    // into G, L^{-1} into G's first m columns (column q of L^{-1} in column q)
+    ldl_columns<MM>(s.G, s.mp, m, n + 1, true, s.G, s.mp,
+                    d.chol ? d.chol + (size_t)t * m * m : nullptr, s.E, s.bad);
     if (!fail && *s.bad) fail = t + 1;
-    ldl_scale(s.G, W, m, WX, 0, s.d);
-    __syncthreads();
-    stage_value(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
+    stage_value<MM, MF>(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
                 d.p ? d.p + (size_t)t * n : nullptr);
-    __syncthreads();
-    // [K | k] = -H^{-1}[S + B'PA | r + B'(Pc+p)]: back substitution with L'
-    ltrsv_cols(s.G, W, m, 0, m, m + n + 1);
-    __syncthreads();
-    double* Kt = d.K + (size_t)t * m * n;
-    double* kt = d.k + (size_t)t * m;
-    for (int e = threadIdx.x; e < m * n; e += kThreads) {
-      const int i = e / n, j = e - i * n;
-      Kt[e] = -s.G[i * W + m + j];
+    {  // [K | k] = -H^{-1}[H_ux | h_u] = -(L^{-1})' Z
+      double* Kt = d.K + (size_t)t * m * n;
+      double* kt = d.k + (size_t)t * m;
+      const int mp = s.mp;
+      pgemm_sub<MF, false, false, false, true>(m, n + 1, 0, s.G, mp, s.G, mp, m, s.G, mp, s.G + m * mp, mp,
+          [=](int i, int j, double v) {
+            if (j < n)
+              Kt[i * n + j] = v;
+            else
+              kt[i] = v;
+          });
     }
-    for (int i = threadIdx.x; i < m; i += kThreads) kt[i] = -s.G[i * W + m + n];
-    if (d.chol) {
-      double* Lt = d.chol + (size_t)t * m * m;
-      for (int e = threadIdx.x; e < m * m; e += kThreads) {
-        const int i = e / m, j = e - i * m;
-        Lt[e] = (i >= j) ? s.G[j * W + i] : 0.0;
-      }
-    }
+    __syncthreads();
   }
-  __syncthreads();
   return fail;
 }
 
@@ -182,6 +192,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
 //   Psi += Z_W'Z_W,  psi += Gam'c - Z_W'z_h,  Gam <- A'Gam - Z_ux'Z_W
 // (Gam' is the closed-loop transition of the segment). Writes
 // P0 | Gam | Psi | pbar | psi to `out`. Returns as plain_sweep.
+template <int MM, bool MF>
 LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const SweepLds& s) {
   const int n = d.n, m = d.m, W = s.W, WX = s.WX;
   double* Gam = s.Y + WX;  // columns [WX, WX+n) of Y
@@ -197,7 +208,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
     __syncthreads();
-    stage_products(d, s);
+    stage_products<MM, MF>(d, s);
     {  // gc = Gam' c_t (Gam of stage t+1)
       const double* X = s.X;
       for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -207,19 +218,17 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
       }
     }
     __syncthreads();
-    stage_hessian(d, t, s, W);
+    stage_hessian<MM, MF>(d, t, s, W);
     __syncthreads();
-    ldl_forward(s.G, W, m, W, 0, s.d, s.bad);
+    ldl_columns<MM>(s.G, s.mp, m, 2 * n + 1, false, nullptr, 0, nullptr, s.E, s.bad);
     if (!fail && *s.bad) fail = t + 1;
-    ldl_scale(s.G, W, m, W, 0, s.d);
-    __syncthreads();
-    stage_value(d, t, s, nullptr, nullptr);
+    stage_value<MM, MF>(d, t, s, nullptr, nullptr);
     {  // [psi-part | Psi-part] = Z_W' [z_h | Z_W]
       double* Psi = s.Psi;
       double* psi = s.psi;
       const double* gc = s.gc;
-      gemm<4, 4, true, false>(
-          n, n + 1, m, s.G + WX, W, s.G + m + n, W,
+      const int mp = s.mp;
+      pgemm_sub<MF, false, true, false, false>(n, n + 1, m, s.G + WX * mp, mp, s.G + (m + n) * mp, mp, 0, s.G, mp, s.G, mp,
           [=](int i, int j, double v) {
             if (j == 0) {
               psi[i] += gc[i] - v;
@@ -230,13 +239,13 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
               Psi[jj * n + i] = nv;
             }
           },
-          SkipUpperShift<4, 4>{n, 1});
+          SkipUpperShift{n, 1});
     }
     __syncthreads();
     {  // Gam_new = A'Gam - Z_ux'Z_W  -> the (now free) P A region of Y
       double* Ynew = s.Y + m;
-      gemm_sub<4, 4, true, false, true, false>(
-          n, n, n, s.X + m, WX, Gam, W, m, s.G + m, W, s.G + WX, W,
+      const int mp = s.mp;
+      pgemm_sub<MF, true, false, false, true>(n, n, n, s.X + m, WX, Gam, W, m, s.G + m * mp, mp, s.G + WX * mp, mp,
           [=](int i, int j, double v) { Ynew[i * W + j] = v; });
     }
     __syncthreads();
@@ -311,17 +320,18 @@ LQR_DEV void write_terminal(const InstDesc& d) {
     for (int i = threadIdx.x; i < n; i += kThreads) d.p[(size_t)T * n + i] = d.q[(size_t)T * n + i];
 }
 
+template <int MM, bool MF>
 LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
   const int n = d.n, m = d.m, T = d.T, J = d.J;
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   int fail;
   if (seg < J - 1) {
-    SweepLds s = carve_sweep(smem, n, m, true);
-    fail = dual_sweep(d, t0, t1, ws_seg(d.ws, n, seg), s);
+    SweepLds s = carve_sweep(smem, n, m, true, MM);
+    fail = dual_sweep<MM, MF>(d, t0, t1, ws_seg(d.ws, n, seg), s);
   } else {
-    SweepLds s = carve_sweep(smem, n, m, false);
+    SweepLds s = carve_sweep(smem, n, m, false, MM);
     write_terminal(d);
-    fail = plain_sweep(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
+    fail = plain_sweep<MM, MF>(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
     double* b = ws_bnd(d.ws, n, J, J - 1);
     store_block(b, n, s.P, n, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = s.p[i];
@@ -335,26 +345,27 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
 // which is the elimination of x_{t_{j+1}} and the link multiplier
 // mu_j = (I + Pn Psi_j)^{-1}(Pn (Gam_j' x + psi_j) + pn) from the segment's
 // value; forward, x_{t_{j+1}} = F x_{t_j} + f.
+template <int MN, bool MF>
 LQR_DEV void couple_item(const InstDesc& d, double* smem) {
-  const int n = d.n, J = d.J, LDN = 2 * n + 1;
-  double* sPn = smem;
+  const int n = d.n, J = d.J;
+  const int mp = MN + 1, MX = MN;
+  double* sPn = smem;                 // n x n row-major
   double* spn = sPn + n * n;
-  double* sA1 = spn + n;
-  double* sN = sA1 + n * n;
-  double* sv = sN + n * LDN;
-  double* sf = sv + n;
-  double* sx = sf + n;
+  double* sA1 = spn + n;              // n x n row-major: Psi, then Gam
+  double* sN = sA1 + n * n;           // mp x (2n+1) column-major: [N | Gam' | w] -> [T1 | F | f]
+  double* sv = sN + mp * (2 * n + 1);
+  double* sx = sv + n;
   double* sxn = sx + n;
-  double* sdp = sxn + n;
-  int* ipiv = reinterpret_cast<int*>(sdp + n);
-  int* used = ipiv + n;
-  int* flag = used + n;
+  double* gjb = sxn + n;              // Gauss-Jordan exchange: 3 * MX + 2
+  int* prow = reinterpret_cast<int*>(gjb + 3 * MX + 2);
+  int* flag = prow + MX;
 
   if (threadIdx.x == 0) {
     int f = 0;
     for (int j = 0; j < J; ++j) f = max(f, d.fail[j]);
     flag[0] = f;  // stage failure from phase 1
     flag[1] = 0;  // linking failure
+    flag[2] = 0;  // pivot flag of the current boundary
   }
   {
     const double* bl = ws_bnd(d.ws, n, J, J - 1);
@@ -369,81 +380,38 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
     const double* pbar = sg + 3 * n * n;
     const double* psi = pbar + n;
     load_block(sA1, n, Psi, n, n, n);
-    for (int i = threadIdx.x; i < n; i += kThreads) used[i] = 0;
-    __syncthreads();
-    gemm<4, 4, false, false>(n, n, n, sA1, n, sPn, n, [=](int i, int jj, double v) {
-      sN[i * LDN + jj] = v + (i == jj ? 1.0 : 0.0);
-    });
-    load_block_t(sN + n, LDN, Gam, n, n, n);
-    gemv2(n, n, sA1, n, spn, 0, spn, 0, spn, [=](int i, double v) { sN[i * LDN + 2 * n] = psi[i] - v; });
-    __syncthreads();
-    load_block(sA1, n, Gam, n, n, n);
-    for (int k = 0; k < n; ++k) {
-      if (threadIdx.x < 64) {
-        double best = -1.0;
-        int bi = 0x7fffffff;
-        for (int i = threadIdx.x; i < n; i += 64) {
-          if (used[i]) continue;
-          double a = fabs(sN[i * LDN + k]);
-          if (!(a <= 1.7976931348623157e308)) a = __builtin_inf();
-          if (a > best || (a == best && i < bi)) {
-            best = a;
-            bi = i;
-          }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
-        if (threadIdx.x == 0) {
-          double dk = sN[bi * LDN + k];
-          if (!(dk != 0.0) || !isfinite(dk)) {
-            if (!flag[1]) flag[1] = LQR_INFO_COUPLING + j;
-            dk = qnan<double>();
-          }
-          ipiv[k] = bi;
-          sdp[k] = dk;
-          used[bi] = 1;
-        }
-      }
-      __syncthreads();
-      const int pr = ipiv[k];
-      const double inv = 1.0 / sdp[k];
-      const int nc = LDN - k - 1;  // columns k+1 .. 2n
-      for (int e = threadIdx.x; e < n * nc; e += kThreads) {
-        const int i = e / nc, jc = k + 1 + (e - i * nc);
-        if (i == pr) continue;
-        sN[i * LDN + jc] = fma(-sN[i * LDN + k] * inv, sN[pr * LDN + jc], sN[i * LDN + jc]);
-      }
-      __syncthreads();
+    // Gam' into columns [n, 2n) of sN: column n + r holds row r of Gam
+    for (int e = threadIdx.x; e < n * n; e += kThreads) {
+      const int r = e / n, i = e - r * n;
+      sN[(n + r) * mp + i] = Gam[e];
     }
-    {  // unpermute and scale: F -> sN[:, 0:n], f -> sf; also to the workspace
+    __syncthreads();
+    pgemm_sub<MF, false, false, false, false>(n, n, n, sA1, n, sPn, n, 0, sA1, n, sPn, n,
+                                          [=](int i, int jj, double v) {
+                                            sN[jj * mp + i] = v + (i == jj ? 1.0 : 0.0);
+                                          });
+    gemv2(n, n, sA1, n, spn, 0, spn, 0, spn,
+          [=](int i, double v) { sN[2 * n * mp + i] = psi[i] - v; });
+    __syncthreads();
+    load_block(sA1, n, Gam, n, n, n);  // Psi no longer needed
+    gj_columns<MN>(sN, mp, n, 2 * n + 1, gjb, prow, flag + 2);
+    {  // [F | f] to the workspace for the forward pass
       double* lk = ws_link(d.ws, n, J, j);
       for (int e = threadIdx.x; e < n * (n + 1); e += kThreads) {
-        const int k = e / (n + 1), c = e - k * (n + 1);
-        const double v = sN[ipiv[k] * LDN + n + c] / sdp[k];
-        if (c < n) {
-          sN[k * LDN + c] = v;
-          lk[k * n + c] = v;
-        } else {
-          sf[k] = v;
-          lk[n * n + k] = v;
-        }
+        const int c = e / n, r = e - c * n;  // column c of [F | f], row r
+        const double v = sN[(n + c) * mp + r];
+        if (c < n)
+          lk[r * n + c] = v;
+        else
+          lk[n * n + r] = v;
       }
     }
+    // T1 = Pn F -> sN columns [0, n) ;  v = pn + Pn f
+    pgemm_sub<MF, false, true, false, false>(n, n, n, sPn, n, sN + n * mp, mp, 0, sPn, n, sN, mp,
+                                         [=](int i, int jj, double v) { sN[jj * mp + i] = v; });
+    gemv2(n, n, sPn, n, sN + 2 * n * mp, 0, spn, 0, spn, [=](int i, double v) { sv[i] = spn[i] + v; });
     __syncthreads();
-    gemm<4, 4, false, false>(n, n, n, sPn, n, sN, LDN, [=](int i, int jj, double v) {
-      sN[i * LDN + n + jj] = v;
-    });
-    gemv2(n, n, sPn, n, sf, 0, sf, 0, sf, [=](int i, double v) { sv[i] = spn[i] + v; });
-    __syncthreads();
-    gemm<4, 4, false, false>(
-        n, n, n, sA1, n, sN + n, LDN,
+    pgemm_sub<MF, false, true, false, false>(n, n, n, sA1, n, sN, mp, 0, sA1, n, sN, mp,
         [=](int i, int jj, double v) {
           if (i >= jj) {
             v += 0.5 * (P0[i * n + jj] + P0[jj * n + i]);
@@ -451,9 +419,10 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
             sPn[jj * n + i] = v;
           }
         },
-        SkipUpper<4, 4>{n});
+        SkipUpper{n});
     gemv2(n, n, sA1, n, sv, 0, sv, 0, sv, [=](int i, double v) { spn[i] = pbar[i] + v; });
     __syncthreads();
+    if (threadIdx.x == 0 && flag[2] && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
     double* b = ws_bnd(d.ws, n, J, j);
     store_block(b, n, sPn, n, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = spn[i];
@@ -478,113 +447,45 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   if (threadIdx.x == 0) *d.info = flag[0] ? flag[0] : flag[1];
 }
 
+template <int MM, bool MF>
 LQR_DEV void phase3_item(const InstDesc& d, int seg, double* smem) {
   const int n = d.n, m = d.m, T = d.T, J = d.J;
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   if (seg < J - 1) {
-    SweepLds s = carve_sweep(smem, n, m, false);
+    SweepLds s = carve_sweep(smem, n, m, false, MM);
     const double* b = ws_bnd(d.ws, n, J, seg + 1);
-    const int fail = plain_sweep(d, t0, t1, b, b + n * n, s);
+    const int fail = plain_sweep<MM, MF>(d, t0, t1, b, b + n * n, s);
     if (fail && threadIdx.x == 0) atomicMax(d.info, fail);
   }
   rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
 }
 
+template <int MM, bool MF>
 LQR_DEV void serial_item(const InstDesc& d, double* smem) {
   const int n = d.n, m = d.m, T = d.T;
-  SweepLds s = carve_sweep(smem, n, m, false);
+  SweepLds s = carve_sweep(smem, n, m, false, MM);
   write_terminal(d);
-  const int fail = plain_sweep(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
+  const int fail = plain_sweep<MM, MF>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
   rollout(d, 0, T, d.x0, true, smem);
   if (threadIdx.x == 0) *d.info = fail;
 }
 
-}  // namespace
 
-__global__ __launch_bounds__(kThreads) void k_phase1(InstDesc d) {
-  extern __shared__ double smem[];
-  phase1_item(d, blockIdx.x, smem);
-}
-__global__ __launch_bounds__(kThreads) void k_phase2(InstDesc d) {
-  extern __shared__ double smem[];
-  couple_item(d, smem);
-}
-__global__ __launch_bounds__(kThreads) void k_phase3(InstDesc d) {
-  extern __shared__ double smem[];
-  phase3_item(d, blockIdx.x, smem);
-}
-__global__ __launch_bounds__(kThreads) void k_serial(InstDesc d) {
-  extern __shared__ double smem[];
-  serial_item(d, smem);
-}
-
-__global__ __launch_bounds__(kThreads) void k_phase1_b(const InstDesc* descs, const WorkItem* items) {
-  extern __shared__ double smem[];
-  const WorkItem w = items[blockIdx.x];
-  phase1_item(descs[w.inst], w.seg, smem);
-}
-__global__ __launch_bounds__(kThreads) void k_phase2_b(const InstDesc* descs) {
-  extern __shared__ double smem[];
-  couple_item(descs[blockIdx.x], smem);
-}
-__global__ __launch_bounds__(kThreads) void k_phase3_b(const InstDesc* descs, const WorkItem* items) {
-  extern __shared__ double smem[];
-  const WorkItem w = items[blockIdx.x];
-  phase3_item(descs[w.inst], w.seg, smem);
-}
-__global__ __launch_bounds__(kThreads) void k_serial_b(const InstDesc* descs) {
-  extern __shared__ double smem[];
-  serial_item(descs[blockIdx.x], smem);
-}
-
-// ---------------------------------------------------------------------------
-// Host-side launchers.
-// ---------------------------------------------------------------------------
-static hipError_t allow_lds(const void* fn, size_t bytes) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-hipError_t launch_parallel(const InstDesc& d, size_t lds1, size_t lds2, size_t lds3,
-                           hipStream_t stream) {
-  hipError_t e;
-  if ((e = allow_lds((const void*)k_phase1, lds1)) != hipSuccess) return e;
-  if ((e = allow_lds((const void*)k_phase2, lds2)) != hipSuccess) return e;
-  if ((e = allow_lds((const void*)k_phase3, lds3)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase1, dim3(d.J), dim3(kThreads), lds1, stream, d);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase2, dim3(1), dim3(kThreads), lds2, stream, d);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase3, dim3(d.J), dim3(kThreads), lds3, stream, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_serial(const InstDesc& d, size_t lds, hipStream_t stream) {
-  hipError_t e;
-  if ((e = allow_lds((const void*)k_serial, lds)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_serial, dim3(1), dim3(kThreads), lds, stream, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items, int nitems,
-                                   int ninst, size_t lds1, size_t lds2, size_t lds3,
-                                   hipStream_t stream) {
-  hipError_t e;
-  if ((e = allow_lds((const void*)k_phase1_b, lds1)) != hipSuccess) return e;
-  if ((e = allow_lds((const void*)k_phase2_b, lds2)) != hipSuccess) return e;
-  if ((e = allow_lds((const void*)k_phase3_b, lds3)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase1_b, dim3(nitems), dim3(kThreads), lds1, stream, descs, items);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase2_b, dim3(ninst), dim3(kThreads), lds2, stream, descs);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase3_b, dim3(nitems), dim3(kThreads), lds3, stream, descs, items);
-  return hipGetLastError();
-}
-
-hipError_t launch_serial_batched(const InstDesc* descs, int ninst, size_t lds, hipStream_t stream) {
-  hipError_t e;
-  if ((e = allow_lds((const void*)k_serial_b, lds)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_serial_b, dim3(ninst), dim3(kThreads), lds, stream, descs);
-  return hipGetLastError();
+// Descriptor of the work a workgroup runs: a single instance passed by value,
+// or an (instance, segment) item of a batched launch's device tables.
+LQR_DEV void select_item(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                         InstDesc& d, int& seg) {
+  if (items) {
+    const WorkItem w = items[blockIdx.x];
+    d = descs[w.inst];
+    seg = w.seg;
+  } else if (descs) {
+    d = descs[blockIdx.x];
+    seg = 0;
+  } else {
+    d = single;
+    seg = blockIdx.x;
+  }
 }
 
 }  // namespace lqr

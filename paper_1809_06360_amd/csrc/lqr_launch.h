@@ -1,0 +1,34 @@
+// Kernel-variant selection and per-phase launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lqr_layout.h"
+
+namespace lqr {
+
+// Call f with the kernel instantiation K<pad_rows(width), mf>.
+template <template <int, bool> class K, typename F>
+hipError_t with_variant(int width, bool mf, F f) {
+  switch (pad_rows(width)) {
+#define LQR_CASE(W) \
+  case W:           \
+    return mf ? f(K<W, true>::fn()) : f(K<W, false>::fn());
+    LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
+#undef LQR_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// One launcher per kernel. `single` is used when descs == nullptr; otherwise
+// workgroup b runs items[b] (phases 1, 3) or descs[b] (phase 2, serial).
+hipError_t launch_k_phase1(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+hipError_t launch_k_phase2(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+hipError_t launch_k_phase3(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+hipError_t launch_k_serial(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
+                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+
+}  // namespace lqr

@@ -5,10 +5,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#ifndef LQR_HD
 #if defined(__HIPCC__)
 #define LQR_HD __host__ __device__ inline
 #else
 #define LQR_HD inline
+#endif
 #endif
 
 namespace lqr {
@@ -63,26 +65,50 @@ LQR_HD double* ws_link(double* ws, int n, int J, int j) {
 //  sp  n               value gradient
 //  sX  n x (m+n+1)     [B_t | A_t | c_t]
 //  sY  n x W           [P B | P A | P c + p | Gamma]          (Gamma: dual sweep only)
-//  sG  m x W           [R + B'PB | S + B'PA | r + B'(Pc+p) | B'Gamma]
+//  sG  mp x W          [R + B'PB | S + B'PA | r + B'(Pc+p) | B'Gamma], column-major
+//                      with leading dimension mp = pad_rows(m) + 1
 //  dual only: sPsi n x n, spsi n, sgc n
-//  sd  m pivots, flags
+//                      (after the elimination its first m columns hold L^{-1})
+//  sE  3 pad_rows(m)   elimination exchange vectors and pivots
+//  dual only: sPsi n x n, spsi n, sgc n
 // with W = m + n + 1 (+ n for the dual sweep).
 LQR_HD int sweep_w(int n, int m, bool dual) { return m + n + 1 + (dual ? n : 0); }
 
-LQR_HD size_t sweep_lds(int n, int m, bool dual) {
-  const size_t W = (size_t)sweep_w(n, m, dual);
-  size_t dbl = (size_t)n * n + n + (size_t)n * (m + n + 1) + (size_t)n * W + (size_t)m * W + m;
+// Column-owner elimination of the input Hessian (see ldl_columns): one thread
+// per column of [H | right-hand sides (| identity)], at most 256 columns, and
+// m <= 64 rows held in registers.
+LQR_HD bool sweep_fits_regs(int n, int m, bool dual) {
+  const int cols = dual ? m + 2 * n + 1 : 2 * m + n + 1;
+  return m <= 64 && cols <= 256;
+}
+
+LQR_HD int pad_rows(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 24 ? 24 : m <= 32 ? 32 : m <= 48 ? 48 : 64; }
+
+// `mw` is the register width of the kernel variant that runs the sweep
+// (pad_rows of the largest m in the launch).
+LQR_HD size_t sweep_lds(int n, int m, bool dual, int mw) {
+  const size_t W = (size_t)sweep_w(n, m, dual), mp = (size_t)mw + 1;
+  size_t dbl = (size_t)n * n + n + (size_t)n * (m + n + 1) + (size_t)n * W + mp * W +
+               3 * (size_t)mw;
   if (dual) dbl += (size_t)n * n + 2 * (size_t)n;
   return dbl * 8 + 64;
 }
 
-// Linking solve: sPn n x n, spn n, sA1 n x n, sN n x (2n+1), vectors, pivots.
-LQR_HD size_t couple_lds(int n) {
-  const size_t dbl = 2 * (size_t)n * n + (size_t)n * (2 * n + 1) + 6 * (size_t)n;
-  return dbl * 8 + 2 * (size_t)n * 4 + 64;
-}
+// Problems with at least this many states run their products on matrix cores.
+constexpr int kMfmaMinN = 32;
+
+// Linking solve: sPn n x n, spn n, sA1 n x n, sN mp x (2n+1) column-major
+// (mp = pad_rows(n) + 1), vectors, Gauss-Jordan exchange (3 pad + 2), pivots.
+LQR_HD size_t couple_lds(int n, int nw);
 
 // Forward simulation: x_t and x_{t+1} (n each), u_t (m).
 LQR_HD size_t rollout_lds(int n, int m) { return (2 * (size_t)n + m) * 8 + 64; }
+
+// `nw` is the register width of the kernel variant (pad_rows of the largest n).
+LQR_HD size_t couple_lds(int n, int nw) {
+  const size_t mx = (size_t)nw, mp = mx + 1;
+  const size_t dbl = 2 * (size_t)n * n + 4 * (size_t)n + mp * (2 * n + 1) + 3 * mx + 2;
+  return dbl * 8 + (mx + 4) * 4 + 64;
+}
 
 }  // namespace lqr

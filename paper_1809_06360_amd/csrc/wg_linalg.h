@@ -12,6 +12,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "lqr_layout.h"
+
 #define LQR_DEV __device__ __forceinline__
 
 namespace lqr {
@@ -38,24 +40,25 @@ LQR_DEV T el(const T* p, int ld, int i, int j) {
 // upper tiles of a symmetric result).
 // ---------------------------------------------------------------------------
 struct NoSkip {
-  LQR_DEV bool operator()(int, int) const { return false; }
+  LQR_DEV bool operator()(int, int, int, int) const { return false; }
 };
 
-// Drop tiles lying strictly above the diagonal of the leading `ns` x `ns`
-// block. A tile is dropped only if all its columns lie inside that block, so
-// tiles that also hold columns >= ns are always computed.
-template <int RM, int RN>
+// Drop tiles (rows i0.., columns j0.., extent tm x tn) lying strictly above the
+// diagonal of the leading `ns` x `ns` block. A tile is dropped only if all its
+// columns lie inside that block, so tiles that also hold columns >= ns are
+// always computed.
 struct SkipUpper {
   int ns;
-  LQR_DEV bool operator()(int i0, int j0) const { return j0 + RN <= ns && j0 > i0 + RM - 1; }
+  LQR_DEV bool operator()(int i0, int j0, int tm, int tn) const {
+    return j0 + tn <= ns && j0 > i0 + tm - 1;
+  }
 };
 
 // Same, for a symmetric block stored in output columns [coff, coff + ns).
-template <int RM, int RN>
 struct SkipUpperShift {
   int ns, coff;
-  LQR_DEV bool operator()(int i0, int j0) const {
-    return j0 >= coff && j0 + RN <= coff + ns && j0 - coff > i0 + RM - 1;
+  LQR_DEV bool operator()(int i0, int j0, int tm, int tn) const {
+    return j0 >= coff && j0 + tn <= coff + ns && j0 - coff > i0 + tm - 1;
   }
 };
 
@@ -69,7 +72,7 @@ LQR_DEV void gemm_sub(int M, int N,
   const int tiles = ((M + RM - 1) / RM) * tn;
   for (int tile = threadIdx.x; tile < tiles; tile += kThreads) {
     const int i0 = (tile / tn) * RM, j0 = (tile % tn) * RN;
-    if (skip(i0, j0)) continue;
+    if (skip(i0, j0, RM, RN)) continue;
     int ii[RM], jj[RN];
 #pragma unroll
     for (int r = 0; r < RM; ++r) ii[r] = min(i0 + r, M - 1);
@@ -185,70 +188,293 @@ LQR_DEV void gemv2(int rows, int c1, const T* M1, int ld1, const T* v1,
 }
 
 // ---------------------------------------------------------------------------
-// Square-root-free Cholesky (L D L') of the symmetric block
-// H = G[0:m, h0:h0+m], carried out as forward elimination on every column of
-// G (m rounds, one barrier each). Only H's upper triangle is read. On return
-// d[k] (LDS) holds the k-th pivot; row k of G holds (D L')[k, :] in the H
-// block (columns h0+k .. h0+m-1) and (L^{-1}_unit X)[k, :] in every column
-// outside the H block. A pivot that is not positive or not finite is
-// replaced by NaN (which then propagates into every dependent result) and
-// the stage is reported through *bad (LDS int, set to 1).
-// Requires a barrier between G's producer and this call.
+// Cross-lane helpers.
 // ---------------------------------------------------------------------------
-template <typename T>
-LQR_DEV void ldl_forward(T* G, int ldg, int m, int ncols, int h0, T* d, int* bad) {
-  for (int k = 0; k < m; ++k) {
-    T dk = G[k * ldg + h0 + k];
-    if (!(dk > T(0)) || !isfinite(dk)) {
-      dk = qnan<T>();
-      if (threadIdx.x == 0) *bad = 1;
-    }
-    if (threadIdx.x == 0) d[k] = dk;
-    const T inv = T(1) / dk;
-    const int rows = m - k - 1;
-    if (rows > 0) {
-      // thread -> (column j, row phase); `tpc` threads share a column
-      const int tpc = max(1, min(rows, kThreads / ncols));
-      for (int idx = threadIdx.x; idx < ncols * tpc; idx += kThreads) {
-        const int j = idx % ncols, ph = idx / ncols;
-        const int jh = j - h0;                 // column index inside H, if in H
-        const bool inH = (jh >= 0 && jh < m);
-        if (inH && jh <= k) continue;          // finished columns of H
-        const int ilast = inH ? jh : m - 1;    // H: upper triangle only
-        const T gkj = G[k * ldg + j] * inv;
-        for (int i = k + 1 + ph; i <= ilast; i += tpc)
-          G[i * ldg + j] = fma(-G[k * ldg + h0 + i], gkj, G[i * ldg + j]);
+// Value of v in lane `lane` (uniform lane index) broadcast to the wave.
+LQR_DEV double readlane(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Register capacity for an m x m factor: 8, 16, 32 or 64 (m <= 64). Blocks
+// handed to the factorization routines use this as their leading dimension,
+// so every unrolled access has a compile-time offset.
+// ---------------------------------------------------------------------------
+LQR_HD int pad_m(int m) { return pad_rows(m); }
+// Leading dimension used with capacity MAXM: one more than MAXM, so that a
+// column walk by 16 lanes hits distinct LDS banks.
+LQR_HD int pad_ld(int m) { return pad_rows(m) + 1; }
+
+// ---------------------------------------------------------------------------
+// Square-root-free Cholesky (L D L') of the m x m input Hessian H, carried out
+// as forward elimination on a set of right-hand sides. Thread c owns "virtual
+// column" c in registers: [0, m) = the columns of H, [m, m + nr) = right-hand
+// sides (the same columns of G), and, if `ident`, [m + nr, 2m + nr) = the
+// identity (not stored in G). G is column-major in LDS with leading dimension
+// ldg. Round k (m rounds, one barrier each): the owner of H's column k
+// publishes the pivot d_k and the multipliers H(i, k)/d_k (i > k) to a
+// double-buffered LDS vector; every column c > k of H and every right-hand
+// side then updates its rows i > k with its own row-k entry. The round loop is
+// unrolled for m <= MAXM so all register indices are compile-time.
+//
+// On return (ends with a barrier):
+//   Z = L^{-1} X  for every right-hand side X (L = L_unit D^{1/2} the
+//     Cholesky factor), written to G's columns [m, m + nr);
+//   if ident: L^{-1} written to zi (column q of L^{-1} at zi + q * ldzi);
+//   if chol != nullptr: L written row-major to chol (m x m, zeros above).
+// A pivot that is not positive or not finite is replaced by NaN (which then
+// propagates into every dependent result) and *bad is set to 1.
+// buf: 3 * MAXM doubles of LDS. Requires 2m + nr (or m + nr) <= 256 and a
+// barrier between G's producer and this call.
+// ---------------------------------------------------------------------------
+template <int MAXM>
+LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* zi, int ldzi,
+                         double* chol, double* buf, int* bad) {
+  // Rows m..MAXM-1 are zero padding, so the unrolled round body needs no
+  // per-element guards: padded multipliers are zero and padded rows stay zero.
+  const int c = threadIdx.x;
+  const int nvc = m + nr + (ident ? m : 0);
+  const bool own = c < nvc;
+  const bool isH = c < m;
+  const bool fromG = c < m + nr;
+  const int q = c - m - nr;
+  const double* src = G + (fromG ? c : 0) * ldg;
+  double* piv = buf + 2 * MAXM;
+  double v[MAXM];
+#pragma unroll
+  for (int i = 0; i < MAXM; ++i) {
+    const double g = src[i];
+    v[i] = (own && i < m) ? (fromG ? g : (i == q ? 1.0 : 0.0)) : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < MAXM; ++k) {
+    if (k < m) {
+      double* cb = buf + (k & 1) * MAXM;
+      if (c == k) {
+        double dk = v[k];
+        if (!(dk > 0.0) || !isfinite(dk)) {
+          dk = qnan<double>();
+          *bad = 1;
+        }
+        piv[k] = dk;
+        const double inv = 1.0 / dk;
+#pragma unroll
+        for (int i = k + 1; i < MAXM; ++i) cb[i] = v[i] * inv;
+      }
+      __syncthreads();
+      if (own && (!isH || c > k)) {
+        const double rk = v[k];
+#pragma unroll
+        for (int i = k + 1; i < MAXM; ++i) v[i] = fma(-cb[i], rk, v[i]);
       }
     }
-    __syncthreads();
   }
-}
-
-// After ldl_forward (and a barrier): divide row k by sqrt(d[k]) so that the H
-// block's upper triangle becomes L' (L the lower Cholesky factor) and the other
-// columns become L^{-1} X.
-template <typename T>
-LQR_DEV void ldl_scale(T* G, int ldg, int m, int ncols, int h0, const T* d) {
-  for (int e = threadIdx.x; e < m * ncols; e += kThreads) {
-    const int k = e / ncols, j = e - k * ncols;
-    const int jh = j - h0;
-    if (jh >= 0 && jh < k) continue;
-    G[k * ldg + j] *= T(1) / sqrt(d[k]);
-  }
-}
-
-// Solve L' X = Z in place for the columns [c0, c1) of G, where L' is the upper
-// triangle of the H block (after ldl_scale) and Z the current column content.
-// One thread per column walks the triangle (no barriers inside).
-template <typename T>
-LQR_DEV void ltrsv_cols(T* G, int ldg, int m, int h0, int c0, int c1) {
-  for (int j = c0 + threadIdx.x; j < c1; j += kThreads) {
-    for (int k = m - 1; k >= 0; --k) {
-      T s = G[k * ldg + j];
-      for (int l = k + 1; l < m; ++l) s = fma(-G[k * ldg + h0 + l], G[l * ldg + j], s);
-      G[k * ldg + j] = s / G[k * ldg + h0 + k];
+  __syncthreads();
+  if (own) {
+    if (isH) {
+      if (chol) {
+        const double sc = sqrt(piv[c]);
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+          if (i < m) chol[i * m + c] = (i == c) ? sc : (i > c ? v[i] / sc : 0.0);
+      }
+    } else {
+      double* dst = fromG ? G + c * ldg : zi + q * ldzi;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) dst[i] = v[i] / sqrt(i < m ? piv[i] : 1.0);
     }
   }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan elimination with row pivoting of an n x nc column-major block
+// (n <= MAXN <= 64 rows, nc <= 256 columns, leading dimension ldg, in LDS):
+// columns [0, n) hold the square matrix N, the rest are right-hand sides.
+// Thread c owns column c in registers (rows n..MAXN-1 are zero padding). In
+// round k the owner of column k publishes it to a double-buffered LDS vector;
+// every wave then finds the pivot row p (largest magnitude among the rows not
+// yet used) by a wave reduction, and every column c > k eliminates column k
+// from all rows but p. After n rounds
+// the solution row k of N^{-1} X is (row p_k of the right-hand sides) /
+// pivot_k; it is written back to G's rows in natural order (columns [n, nc)),
+// so G[:, n:nc) <- N^{-1} G[:, n:nc). A zero or non-finite pivot is replaced by
+// NaN and *bad is set to 1. buf: 3 * MAXN doubles and MAXN ints of LDS
+// (exchange, pivots, rows). n <= 64 (one row per lane in the pivot search). Requires a barrier between G's producer and this call; ends
+// with a barrier.
+// ---------------------------------------------------------------------------
+// v[p] for a wave-uniform index p (binary search over scalar branches).
+template <int LO, int HI, int MAXN>
+LQR_DEV double pick(const double (&v)[MAXN], int p) {
+  if constexpr (HI - LO == 1) {
+    return v[LO];
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    return p < MID ? pick<LO, MID, MAXN>(v, p) : pick<MID, HI, MAXN>(v, p);
+  }
+}
+
+template <int MAXN>
+LQR_DEV void gj_columns(double* G, int ldg, int n, int nc, double* buf, int* prow, int* bad) {
+  const int c = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool own = c < nc;
+  double* pivs = buf + 2 * MAXN;  // MAXN pivot values
+  double v[MAXN];
+  const double* src = G + (own ? c : 0) * ldg;
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i) {
+    const double g = src[i];
+    v[i] = (own && i < n) ? g : 0.0;
+  }
+  unsigned long long used = 0ull;
+#pragma unroll
+  for (int k = 0; k < MAXN; ++k) {
+    if (k < n) {
+      double* cb = buf + (k & 1) * MAXN;
+      if (c == k) {
+#pragma unroll
+        for (int i = 0; i < MAXN; ++i) cb[i] = v[i];
+      }
+      __syncthreads();
+      // the published column, loaded up front (broadcast reads)
+      double mk[MAXN];
+#pragma unroll
+      for (int i = 0; i < MAXN; ++i) mk[i] = cb[i];
+      // pivot: argmax |column k| over unused rows, by every wave (lane = row).
+      // Key = bits of |value| with the low 6 mantissa bits replaced by
+      // (63 - row): non-negative doubles order like their bit patterns, ties
+      // go to the lowest row, NaN and inf sort first.
+      long long key = -1;
+      if (lane < n && !((used >> lane) & 1ull)) {
+        double a = fabs(cb[lane]);
+        if (!(a <= 1.7976931348623157e308)) a = __builtin_inf();
+        key = (long long)((__builtin_bit_cast(unsigned long long, a) & ~63ull) | (unsigned)(63 - lane));
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+      }
+      const int p = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63));
+      double dp = cb[p];
+      if (!(dp != 0.0) || !isfinite(dp)) {
+        dp = qnan<double>();
+        if (c == k) *bad = 1;
+      }
+      if (c == k) {
+        pivs[k] = dp;
+        prow[k] = p;
+      }
+      used |= 1ull << p;
+      if (own && c > k) {
+        const double rp = pick<0, MAXN, MAXN>(v, p) / dp;
+#pragma unroll
+        for (int i = 0; i < MAXN; ++i) v[i] = (i == p) ? v[i] : fma(-mk[i], rp, v[i]);
+      }
+    }
+  }
+  __syncthreads();
+  if (own && c >= n) {  // un-permute: solution row k is row prow[k] / pivot k
+    double* col = G + c * ldg;
+#pragma unroll
+    for (int i = 0; i < MAXN; ++i)
+      if (i < n) col[i] = v[i];
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k)
+      if (k < n) v[k] = col[prow[k]] / pivs[k];
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k)
+      if (k < n) col[k] = v[k];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 matrix-core product on 16x16 output tiles (v_mfma_f64_16x16x4f64):
+//   v(i, j) = sum_k op(A1)(i,k) op(B1)(k,j) - sum_k op(A2)(i,k) op(B2)(k,j)
+// for 0 <= i < M, 0 <= j < N, handed to epi(i, j, v). Operand layout of the
+// instruction: lane l supplies A(i = l%16, k = l/16) and B(k = l/16, j = l%16);
+// result register r of lane l is D(i = l/16 + 4r, j = l%16). Each wave takes
+// every 4th tile and runs two tiles at a time for two independent
+// accumulation chains; out-of-range operand elements load as zero.
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((vector_size(32)));
+
+// One operand stream of a tile: kc consecutive k-steps (4 k each) of A and B
+// fragments loaded up front (independent LDS reads), then kc MFMAs.
+template <bool TA, bool TB, int KC>
+LQR_DEV void mfma_chunk(f64x4& acc, const double* A, int lda, const double* B, int ldb, int M, int N,
+                        int K, int i, int j, int k0, int lk, double sgn) {
+  double a[KC], b[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) {
+    const int k = k0 + 4 * s + lk;
+    const bool kin = k < K;
+    const int kk = kin ? k : K - 1;
+    a[s] = (kin && i < M) ? sgn * el<TA>(A, lda, i < M ? i : M - 1, kk) : 0.0;
+    b[s] = (kin && j < N) ? el<TB>(B, ldb, kk, j < N ? j : N - 1) : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < KC; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+}
+
+template <bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
+LQR_DEV void mgemm_sub(int M, int N,
+                       int K1, const double* A1, int lda1, const double* B1, int ldb1,
+                       int K2, const double* A2, int lda2, const double* B2, int ldb2,
+                       Epi epi, Skip skip = Skip()) {
+  constexpr int KC = 4;  // k-steps per preloaded chunk (16 k)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tn = (N + 15) >> 4;
+  const int tiles = ((M + 15) >> 4) * tn;
+  for (int t0 = wave; t0 < tiles; t0 += 2 * kWaves) {
+    const int t1 = t0 + kWaves;
+    const bool has1 = t1 < tiles;
+    const int i0a = (t0 / tn) << 4, j0a = (t0 % tn) << 4;
+    const int i0b = has1 ? (t1 / tn) << 4 : i0a, j0b = has1 ? (t1 % tn) << 4 : j0a;
+    const bool runa = !skip(i0a, j0a, 16, 16), runb = has1 && !skip(i0b, j0b, 16, 16);
+    if (!runa && !runb) continue;
+    f64x4 acca = {0.0, 0.0, 0.0, 0.0}, accb = {0.0, 0.0, 0.0, 0.0};
+    const int ia = i0a + li, ja = j0a + li, ib = i0b + li, jb = j0b + li;
+    for (int k0 = 0; k0 < K1; k0 += 4 * KC) {
+      mfma_chunk<TA1, TB1, KC>(acca, A1, lda1, B1, ldb1, M, N, K1, ia, ja, k0, lk, 1.0);
+      if (has1) mfma_chunk<TA1, TB1, KC>(accb, A1, lda1, B1, ldb1, M, N, K1, ib, jb, k0, lk, 1.0);
+    }
+    for (int k0 = 0; k0 < K2; k0 += 4 * KC) {
+      mfma_chunk<TA2, TB2, KC>(acca, A2, lda2, B2, ldb2, M, N, K2, ia, ja, k0, lk, -1.0);
+      if (has1) mfma_chunk<TA2, TB2, KC>(accb, A2, lda2, B2, ldb2, M, N, K2, ib, jb, k0, lk, -1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lk + 4 * r;
+      if (runa && i0a + i < M && j0a + li < N) epi(i0a + i, j0a + li, acca[r]);
+      if (runb && i0b + i < M && j0b + li < N) epi(i0b + i, j0b + li, accb[r]);
+    }
+  }
+}
+
+template <bool TA, bool TB, typename Epi, typename Skip = NoSkip>
+LQR_DEV void mgemm(int M, int N, int K, const double* A, int lda, const double* B, int ldb, Epi epi,
+                   Skip skip = Skip()) {
+  mgemm_sub<TA, TB, false, false>(M, N, K, A, lda, B, ldb, 0, A, lda, B, ldb, epi, skip);
+}
+
+// Product on matrix cores (MF, used when the problem has n >= 32 states) or on
+// the vector ALUs with 4x4 register tiles.
+template <bool MF, bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
+LQR_DEV void pgemm_sub(int M, int N,
+                       int K1, const double* A1, int lda1, const double* B1, int ldb1,
+                       int K2, const double* A2, int lda2, const double* B2, int ldb2,
+                       Epi epi, Skip skip = Skip()) {
+  if constexpr (MF)
+    mgemm_sub<TA1, TB1, TA2, TB2>(M, N, K1, A1, lda1, B1, ldb1, K2, A2, lda2, B2, ldb2, epi, skip);
+  else
+    gemm_sub<4, 4, TA1, TB1, TA2, TB2>(M, N, K1, A1, lda1, B1, ldb1, K2, A2, lda2, B2, ldb2, epi, skip);
 }
 
 }  // namespace lqr

@@ -123,3 +123,13 @@ def test_oversized_problem_is_unsupported_not_crashing():
     with pytest.raises(L.LQRError) as e:
         L.lqr_workspace_size(ctypes.byref(_prob(200, 100, 16, 0)), 1, L.options())
     assert e.value.status == L.ERR_UNSUPPORTED
+
+
+def test_every_named_workload_fits_the_device_limits():
+    """The planner accepts every instance of the named workloads (LDS
+    footprints within the 160 KiB a gfx950 workgroup may allocate)."""
+    from synthetic import WORKLOADS
+    for key in ("small", "large", "batched", "diff"):
+        w = WORKLOADS[key]
+        arr = (L.LqrProblem * w.batch)(*[L.LqrProblem(n, m, T, w.segments) for (n, m, T) in w.dims])
+        assert L.lqr_workspace_size(arr, w.batch, L.options()) > 0, key

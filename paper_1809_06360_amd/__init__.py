@@ -240,3 +240,115 @@ def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "pa
     s = (stream or torch.cuda.current_stream(device)).cuda_stream
     lqr_solve_batched(arr, batch, opts, ws.data_ptr(), ws.numel(), s)
     return outs, ws
+
+
+GRAD_KEYS = ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")
+
+
+def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=None):
+    """Gradients of a loss l(x, u) with respect to the problem data of a batch
+    already solved by ``solve_batched`` (``outs`` must hold K, P, x, u, lam,
+    chol). ``dl_dx[i]``, ``dl_du[i]``: upstream gradients of instance i.
+    Returns a list of dicts of gradient tensors (keys in ``which``)."""
+    import torch
+    batch = len(datas)
+    probs = (LqrProblem * batch)()
+    grads = (LqrGrad * batch)()
+    res = []
+    for i, (data, out) in enumerate(zip(datas, outs)):
+        T, n, m = data["B"].shape
+        for key in ("K", "P", "x", "u", "lam", "chol"):
+            if out.get(key) is None:
+                raise ValueError("backward needs the forward output %r (solve with with_lam=True, "
+                                 "with_chol=True)" % key)
+        probs[i] = _problem(data, out, 0)
+        z = lambda *s: torch.empty(*s, dtype=data["A"].dtype, device=data["A"].device)  # noqa: E731
+        shapes = dict(A=(T, n, n), B=(T, n, m), c=(T, n), Q=(T + 1, n, n), q=(T + 1, n),
+                      R=(T, m, m), r=(T, m), S=(T, m, n), x0=(n,))
+        g = {k: z(*shapes[k]) for k in which}
+        res.append(g)
+        gx, gu = dl_dx[i].contiguous(), dl_du[i].contiguous()
+        g["_keep"] = (gx, gu)
+        grads[i] = LqrGrad(gx.data_ptr(), gu.data_ptr(), *[_ptr(g.get(k)) for k in
+                                                           ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")])
+    opts = options("fp64", "parallel")
+    nbytes = lqr_workspace_size(probs, batch, opts)
+    device = datas[0]["A"].device
+    ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
+    s = (stream or torch.cuda.current_stream(device)).cuda_stream
+    lqr_backward(probs, batch, grads, opts, ws.data_ptr(), ws.numel(), s)
+    for g in res:
+        g["_workspace"] = ws
+    return res
+
+
+def _instances(A, B, c, Q, q, R, r, x0, S=None):
+    """Per-instance views of batched tensors [N, ...] (contiguous)."""
+    N = A.shape[0]
+    out = []
+    for i in range(N):
+        d = dict(A=A[i], B=B[i], c=c[i], Q=Q[i], q=q[i], R=R[i], r=r[i], x0=x0[i])
+        if S is not None:
+            d["S"] = S[i]
+        out.append(d)
+    return out
+
+
+def _lqr_function():
+    import torch
+
+    class LQRFunction(torch.autograd.Function):
+        """Differentiable batched LQR: (A, B, c, Q, q, R, r, x0) -> (x, u).
+
+        Inputs are float64 CUDA tensors with a leading batch dimension N
+        (A [N,T,n,n], B [N,T,n,m], c [N,T,n], Q [N,T+1,n,n], q [N,T+1,n],
+        R [N,T,m,m], r [N,T,m], x0 [N,n]); outputs x [N,T+1,n], u [N,T,m].
+        Forward: one lqr_solve_batched call; backward: one lqr_backward call
+        (adjoint re-solve on the KKT-transposed right-hand side)."""
+
+        @staticmethod
+        def forward(ctx, A, B, c, Q, q, R, r, x0):
+            ts = [t.contiguous() for t in (A, B, c, Q, q, R, r, x0)]
+            N, T, n, m = ts[1].shape[0], ts[1].shape[1], ts[1].shape[2], ts[1].shape[3]
+            dev, dt = ts[0].device, ts[0].dtype
+            e = lambda *s: torch.empty(*s, dtype=dt, device=dev)  # noqa: E731
+            big = dict(K=e(N, T, m, n), k=e(N, T, m), P=e(N, T + 1, n, n), p=e(N, T + 1, n),
+                       x=e(N, T + 1, n), u=e(N, T, m), lam=e(N, T + 1, n), chol=e(N, T, m, m),
+                       info=torch.zeros(N, 1, dtype=torch.int32, device=dev))
+            datas = _instances(*ts)
+            outs = [{k: v[i] for k, v in big.items()} for i in range(N)]
+            solve_batched(datas, outputs=outs)
+            ctx.save_for_backward(*ts)
+            ctx.big = big
+            return big["x"], big["u"]
+
+        @staticmethod
+        def backward(ctx, gx, gu):
+            ts = ctx.saved_tensors
+            big = ctx.big
+            N = ts[0].shape[0]
+            if gx is None:
+                gx = torch.zeros_like(big["x"])
+            if gu is None:
+                gu = torch.zeros_like(big["u"])
+            gx, gu = gx.contiguous(), gu.contiguous()
+            datas = _instances(*ts)
+            outs = [{k: v[i] for k, v in big.items()} for i in range(N)]
+            keys = ("A", "B", "c", "Q", "q", "R", "r", "x0")
+            need = [k for k, flag in zip(keys, ctx.needs_input_grad) if flag]
+            gs = backward(datas, outs, [gx[i] for i in range(N)], [gu[i] for i in range(N)],
+                          which=tuple(need) or ("x0",))
+            result = []
+            for k, flag in zip(keys, ctx.needs_input_grad):
+                result.append(torch.stack([g[k] for g in gs]) if flag else None)
+            return tuple(result)
+
+    return LQRFunction
+
+
+def __getattr__(name):
+    if name == "LQRFunction":
+        fn = _lqr_function()
+        globals()["LQRFunction"] = fn
+        return fn
+    raise AttributeError(name)

@@ -1,0 +1,202 @@
+// Adjoint (gradient) of the LQR solve, FP64.
+//
+// The optimal (x, u, lam) solves the KKT system of eq. (KKT), whose matrix is
+// symmetric; differentiating it shows that the gradient of a loss l(x, u)
+// needs one more solve of the same system against the right-hand side
+// dl/d(x, u): the same LQR with linear terms qhat = -dl/dx, rhat = -dl/du,
+// zero offsets and a zero initial state. Its quadratic data are unchanged, so
+// the forward solve's gains K_t, value Hessians P_t and Cholesky factors L_t of
+// the input Hessians are reused: backward,
+//   hhat_t = rhat_t + B_t' phat_{t+1},   khat_t = -(L_t L_t')^{-1} hhat_t,
+//   phat_t = qhat_t + A_t' phat_{t+1} + K_t' hhat_t,   phat_T = qhat_T
+// (K_t' hhat = H_ux' khat since K = -H_uu^{-1} H_ux), then forward from
+// xhat_0 = 0: uhat_t = K_t xhat_t + khat_t, xhat_{t+1} = A_t xhat_t + B_t uhat_t,
+// lamhat_t = P_t xhat_t + phat_t. The gradients are outer products of the two
+// solutions (see k_adjoint_grad).
+#include "lqr_device.h"
+#include "lqr_launch.h"
+
+namespace lqr {
+
+namespace {
+
+// Solve (L L') y = b in place for one m-vector b in LDS, L row-major (m x m,
+// lower) in global memory; run by wave 0 (lane = row), m sequential steps per
+// triangle with wave-level ordering only.
+LQR_DEV void chol_solve_wave(const double* L, int m, double* b) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < m; ++k) {  // L z = b
+    const double zk = b[k] / L[k * m + k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) b[k] = zk;
+    if (lane > k && lane < m) b[lane] = fma(-L[lane * m + k], zk, b[lane]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int k = m - 1; k >= 0; --k) {  // L' y = z
+    const double yk = b[k] / L[k * m + k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) b[k] = yk;
+    if (lane < k) b[lane] = fma(-L[k * m + lane], yk, b[lane]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+}  // namespace
+
+// One workgroup per instance: the adjoint backward and forward recursions.
+// Workspace per instance (AdjDesc::ws): phat (T+1)n | khat T m | xhat (T+1)n |
+// uhat T m | lamhat (T+1)n.
+__global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs) {
+  extern __shared__ double smem[];
+  const AdjDesc a = descs[blockIdx.x];
+  const int n = a.n, m = a.m, T = a.T;
+  double* ph = a.ws;
+  double* kh = ph + (size_t)(T + 1) * n;
+  double* xh = kh + (size_t)T * m;
+  double* uh = xh + (size_t)(T + 1) * n;
+  double* lh = uh + (size_t)T * m;
+  double* sp = smem;      // phat_{t+1} (n)
+  double* sh = sp + n;    // hhat (m), then khat
+  double* sh2 = sh + m;   // copy of hhat for K' hhat
+  double* sx = sh2 + m;   // xhat_t (n)
+  double* sxn = sx + n;   // xhat_{t+1} (n)
+  double* su = sxn + n;   // uhat_t (m)
+
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const double v = -a.dl_dx[(size_t)T * n + i];
+    sp[i] = v;
+    ph[(size_t)T * n + i] = v;
+  }
+  __syncthreads();
+  for (int t = T - 1; t >= 0; --t) {
+    const double* At = a.A + (size_t)t * n * n;
+    const double* Bt = a.B + (size_t)t * n * m;
+    const double* Kt = a.K + (size_t)t * m * n;
+    // hhat = rhat + B' phat  (column i of B against phat)
+    for (int i = threadIdx.x; i < m; i += kThreads) {
+      double s = -a.dl_du[(size_t)t * m + i];
+      for (int l = 0; l < n; ++l) s = fma(Bt[l * m + i], sp[l], s);
+      sh[i] = s;
+      sh2[i] = s;
+    }
+    __syncthreads();
+    // phat_t = qhat + A' phat + K' hhat   (reads sp, sh2; written below after a barrier)
+    double acc = 0.0;
+    const int i = threadIdx.x;
+    if (i < n) {
+      acc = -a.dl_dx[(size_t)t * n + i];
+      for (int l = 0; l < n; ++l) acc = fma(At[l * n + i], sp[l], acc);
+      for (int l = 0; l < m; ++l) acc = fma(Kt[l * n + i], sh2[l], acc);
+    }
+    if (threadIdx.x < 64) chol_solve_wave(a.chol + (size_t)t * m * m, m, sh);
+    __syncthreads();
+    if (i < n) {
+      sp[i] = acc;
+      ph[(size_t)t * n + i] = acc;
+    }
+    for (int j = threadIdx.x; j < m; j += kThreads) kh[(size_t)t * m + j] = -sh[j];
+    __syncthreads();
+  }
+  // forward: xhat_0 = 0
+  for (int j = threadIdx.x; j < n; j += kThreads) sx[j] = 0.0;
+  __syncthreads();
+  for (int t = 0; t <= T; ++t) {
+    const double* Pt = a.P + (size_t)t * n * n;
+    double* xo = xh + (size_t)t * n;
+    double* lo = lh + (size_t)t * n;
+    for (int j = threadIdx.x; j < n; j += kThreads) xo[j] = sx[j];
+    gemv2(n, n, Pt, n, sx, 0, sx, 0, sx,
+          [=](int r, double v) { lo[r] = ph[(size_t)t * n + r] + v; });
+    if (t == T) break;
+    const double* At = a.A + (size_t)t * n * n;
+    const double* Bt = a.B + (size_t)t * n * m;
+    const double* Kt = a.K + (size_t)t * m * n;
+    gemv2(m, n, Kt, n, sx, 0, sx, 0, sx, [=](int r, double v) {
+      v += kh[(size_t)t * m + r];
+      su[r] = v;
+      uh[(size_t)t * m + r] = v;
+    });
+    __syncthreads();
+    gemv2(n, n, At, n, sx, m, Bt, m, su, [=](int r, double v) { sxn[r] = v; });
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kThreads) sx[j] = sxn[j];
+    __syncthreads();
+  }
+}
+
+// Gradient outer products, one workgroup per (instance, block of stages):
+//   dq_t = -xhat_t, dr_t = -uhat_t, dc_t = -lamhat_{t+1}, dx0 = -lamhat_0,
+//   dQ_t = -(xhat_t x_t' + x_t xhat_t')/2, dR_t = -(uhat_t u_t' + u_t uhat_t')/2,
+//   dS_t = -(uhat_t x_t' + u_t xhat_t'),
+//   dA_t = -(lamhat_{t+1} x_t' + lam_{t+1} xhat_t'),
+//   dB_t = -(lamhat_{t+1} u_t' + lam_{t+1} uhat_t').
+// Every output element is written by exactly one thread with coalesced rows.
+__global__ __launch_bounds__(kThreads) void k_adjoint_grad(const AdjDesc* descs, const int2* blocks) {
+  const int2 bk = blocks[blockIdx.x];
+  const AdjDesc a = descs[bk.x];
+  const int n = a.n, m = a.m, T = a.T;
+  const double* ph = a.ws;
+  const double* xh = ph + (size_t)(T + 1) * n + (size_t)T * m;
+  const double* uh = xh + (size_t)(T + 1) * n;
+  const double* lh = uh + (size_t)T * m;
+  const int t0 = bk.y * kAdjStages, t1 = min(T + 1, t0 + kAdjStages);
+  for (int t = t0; t < t1; ++t) {
+    const double* xt = a.x + (size_t)t * n;
+    const double* xht = xh + (size_t)t * n;
+    if (a.dq)
+      for (int i = threadIdx.x; i < n; i += kThreads) a.dq[(size_t)t * n + i] = -xht[i];
+    if (a.dQ)
+      for (int e = threadIdx.x; e < n * n; e += kThreads) {
+        const int i = e / n, j = e - i * n;
+        a.dQ[(size_t)t * n * n + e] = -0.5 * (xht[i] * xt[j] + xt[i] * xht[j]);
+      }
+    if (t == 0 && a.dx0)
+      for (int i = threadIdx.x; i < n; i += kThreads) a.dx0[i] = -lh[i];
+    if (t == T) continue;
+    const double* ut = a.u + (size_t)t * m;
+    const double* uht = uh + (size_t)t * m;
+    const double* l1 = a.lam + (size_t)(t + 1) * n;
+    const double* lh1 = lh + (size_t)(t + 1) * n;
+    if (a.dr)
+      for (int i = threadIdx.x; i < m; i += kThreads) a.dr[(size_t)t * m + i] = -uht[i];
+    if (a.dc)
+      for (int i = threadIdx.x; i < n; i += kThreads) a.dc[(size_t)t * n + i] = -lh1[i];
+    if (a.dR)
+      for (int e = threadIdx.x; e < m * m; e += kThreads) {
+        const int i = e / m, j = e - i * m;
+        a.dR[(size_t)t * m * m + e] = -0.5 * (uht[i] * ut[j] + ut[i] * uht[j]);
+      }
+    if (a.dS)
+      for (int e = threadIdx.x; e < m * n; e += kThreads) {
+        const int i = e / n, j = e - i * n;
+        a.dS[(size_t)t * m * n + e] = -(uht[i] * xt[j] + ut[i] * xht[j]);
+      }
+    if (a.dA)
+      for (int e = threadIdx.x; e < n * n; e += kThreads) {
+        const int i = e / n, j = e - i * n;
+        a.dA[(size_t)t * n * n + e] = -(lh1[i] * xt[j] + l1[i] * xht[j]);
+      }
+    if (a.dB)
+      for (int e = threadIdx.x; e < n * m; e += kThreads) {
+        const int i = e / m, j = e - i * m;
+        a.dB[(size_t)t * n * m + e] = -(lh1[i] * ut[j] + l1[i] * uht[j]);
+      }
+  }
+}
+
+hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, int nblocks,
+                          size_t lds, hipStream_t stream) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_adjoint_solve,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adjoint_solve, dim3(ninst), dim3(kThreads), lds, stream, descs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adjoint_grad, dim3(nblocks), dim3(kThreads), 0, stream, descs, blocks);
+  return hipGetLastError();
+}
+
+}  // namespace lqr

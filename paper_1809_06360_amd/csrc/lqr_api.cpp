@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lqr_kernels.h"
+#include "lqr_launch.h"
 #include "lqr_layout.h"
 #include "mi355lqr.h"
 
@@ -164,6 +165,37 @@ lqr_status_t check_device(const BatchPlan& plan) {
   return need <= lim ? LQR_SUCCESS : LQR_ERR_UNSUPPORTED;
 }
 
+// Adjoint layout: AdjDesc table, stage-block table, then per-instance scratch.
+struct AdjPlan {
+  size_t table_bytes = 0, blocks_off = 0, total_bytes = 0;
+  int nblocks = 0;
+  std::vector<size_t> ws_off;
+  size_t lds = 0;
+};
+
+lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap) {
+  if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
+  ap->ws_off.resize(batch);
+  int nb = 0;
+  for (int i = 0; i < batch; ++i) {
+    lqr_status_t st = check_dims(probs[i]);
+    if (st != LQR_SUCCESS) return st;
+    if (probs[i].m > 64) return LQR_ERR_UNSUPPORTED;
+    nb += (probs[i].T + 1 + kAdjStages - 1) / kAdjStages;
+    ap->lds = std::max(ap->lds, adj_lds(probs[i].n, probs[i].m));
+  }
+  ap->nblocks = nb;
+  ap->blocks_off = align_up(sizeof(AdjDesc) * (size_t)batch);
+  ap->table_bytes = ap->blocks_off + align_up(sizeof(int2) * (size_t)nb);
+  size_t off = ap->table_bytes;
+  for (int i = 0; i < batch; ++i) {
+    ap->ws_off[i] = off;
+    off += align_up(adj_ws_doubles(probs[i].n, probs[i].m, probs[i].T) * sizeof(double));
+  }
+  ap->total_bytes = off;
+  return LQR_SUCCESS;
+}
+
 InstDesc make_desc(const lqr_problem_t& p, int J, char* ws_base, size_t ws_off) {
   InstDesc d;
   d.n = p.n;
@@ -226,7 +258,10 @@ lqr_status_t lqr_workspace_size(const lqr_problem_t* probs, int32_t batch, const
     BatchPlan plan;
     lqr_status_t st = make_plan(probs, batch, opts, &plan);
     if (st != LQR_SUCCESS) return st;
-    *bytes = plan.total_bytes;
+    size_t need = plan.total_bytes;
+    AdjPlan ap;  // lqr_backward on the same problems uses the same workspace
+    if (make_adj_plan(probs, batch, &ap) == LQR_SUCCESS) need = std::max(need, ap.total_bytes);
+    *bytes = need;
     return LQR_SUCCESS;
   } catch (const std::bad_alloc&) {
     return LQR_ERR_INVALID_ARG;
@@ -347,8 +382,73 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
 
 lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_grad_t* grads,
                           const lqr_options_t* opts, void* ws, size_t ws_bytes, void* stream) {
-  (void)probs; (void)batch; (void)grads; (void)opts; (void)ws; (void)ws_bytes; (void)stream;
-  return LQR_ERR_UNSUPPORTED;
+  try {
+    lqr_status_t st = check_options(opts);
+    if (st != LQR_SUCCESS) return st;
+    if (!grads) return LQR_ERR_INVALID_ARG;
+    AdjPlan ap;
+    if ((st = make_adj_plan(probs, batch, &ap)) != LQR_SUCCESS) return st;
+    for (int i = 0; i < batch; ++i) {
+      const lqr_problem_t& p = probs[i];
+      if (!p.A || !p.B || !p.K || !p.P || !p.x || !p.u || !p.lam || !p.chol) return LQR_ERR_INVALID_ARG;
+      if (!grads[i].dl_dx || !grads[i].dl_du) return LQR_ERR_INVALID_ARG;
+    }
+    if (!ws || ws_bytes < ap.total_bytes) return LQR_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+    char* base = static_cast<char*>(ws);
+    std::vector<char> table(ap.table_bytes, 0);
+    AdjDesc* descs = reinterpret_cast<AdjDesc*>(table.data());
+    int2* blocks = reinterpret_cast<int2*>(table.data() + ap.blocks_off);
+    int nb = 0;
+    for (int i = 0; i < batch; ++i) {
+      const lqr_problem_t& p = probs[i];
+      const lqr_grad_t& g = grads[i];
+      AdjDesc& a = descs[i];
+      a.n = p.n; a.m = p.m; a.T = p.T; a.pad_ = 0;
+      a.A = static_cast<const double*>(p.A);
+      a.B = static_cast<const double*>(p.B);
+      a.K = static_cast<const double*>(p.K);
+      a.P = static_cast<const double*>(p.P);
+      a.chol = static_cast<const double*>(p.chol);
+      a.x = static_cast<const double*>(p.x);
+      a.u = static_cast<const double*>(p.u);
+      a.lam = static_cast<const double*>(p.lam);
+      a.dl_dx = static_cast<const double*>(g.dl_dx);
+      a.dl_du = static_cast<const double*>(g.dl_du);
+      a.dA = static_cast<double*>(g.dA);
+      a.dB = static_cast<double*>(g.dB);
+      a.dc = static_cast<double*>(g.dc);
+      a.dQ = static_cast<double*>(g.dQ);
+      a.dq = static_cast<double*>(g.dq);
+      a.dR = static_cast<double*>(g.dR);
+      a.dr = static_cast<double*>(g.dr);
+      a.dS = static_cast<double*>(g.dS);
+      a.dx0 = static_cast<double*>(g.dx0);
+      a.ws = reinterpret_cast<double*>(base + ap.ws_off[i]);
+      const int nbi = (p.T + 1 + kAdjStages - 1) / kAdjStages;
+      for (int b = 0; b < nbi; ++b) blocks[nb++] = int2{i, b};
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
+    {
+      std::lock_guard<std::mutex> lock(g_plan_mu);
+      if (cap != hipStreamCaptureStatusNone) {
+        auto it = g_plans.find(ws);
+        if (it == g_plans.end() || it->second != table) return LQR_ERR_INVALID_ARG;
+      } else {
+        std::vector<char>& keep = g_plans[ws];
+        keep = table;
+        if (hipMemcpyAsync(ws, keep.data(), keep.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+          return LQR_ERR_HIP;
+      }
+    }
+    hipError_t e = launch_adjoint(reinterpret_cast<const AdjDesc*>(base), batch,
+                                  reinterpret_cast<const int2*>(base + ap.blocks_off), nb, ap.lds, s);
+    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
 }
 
 }  // extern "C"

@@ -31,4 +31,9 @@ hipError_t launch_k_phase3(const InstDesc& single, const InstDesc* descs, const 
 hipError_t launch_k_serial(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
                            unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
 
+// Adjoint solve (one workgroup per instance) followed by the gradient
+// outer products (one workgroup per (instance, kAdjStages stages) block).
+hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, int nblocks,
+                          size_t lds, hipStream_t stream);
+
 }  // namespace lqr

@@ -27,6 +27,25 @@ struct InstDesc {
   int32_t *fail;   // [J] first failing stage + 1 seen by each segment's sweep, 0 if none
 };
 
+// One instance of the adjoint (gradient) computation: forward data and
+// outputs, upstream gradients, gradient outputs (nullptr = not written) and
+// a per-instance scratch area (phat, khat, xhat, uhat, lamhat).
+struct AdjDesc {
+  int32_t n, m, T, pad_;
+  const double *A, *B, *K, *P, *chol, *x, *u, *lam;
+  const double *dl_dx, *dl_du;
+  double *dA, *dB, *dc, *dQ, *dq, *dR, *dr, *dS, *dx0;
+  double* ws;
+};
+
+// Stages per workgroup of the gradient outer-product kernel.
+constexpr int kAdjStages = 8;
+
+LQR_HD size_t adj_ws_doubles(int n, int m, int T) {
+  return 3 * (size_t)(T + 1) * n + 2 * (size_t)T * m;
+}
+LQR_HD size_t adj_lds(int n, int m) { return (3 * (size_t)n + 3 * (size_t)m) * 8 + 64; }
+
 // A unit of batched work: instance index and segment index.
 struct WorkItem {
   int32_t inst, seg;

@@ -133,3 +133,22 @@ def test_every_named_workload_fits_the_device_limits():
         w = WORKLOADS[key]
         arr = (L.LqrProblem * w.batch)(*[L.LqrProblem(n, m, T, w.segments) for (n, m, T) in w.dims])
         assert L.lqr_workspace_size(arr, w.batch, L.options()) > 0, key
+
+
+def test_backward_rejects_bad_arguments():
+    prob = _prob(4, 2, 8, 1)
+    arr = (L.LqrProblem * 1)(prob)
+    grads = (L.LqrGrad * 1)()
+    with pytest.raises(L.LQRError) as e:      # forward outputs missing
+        L.lqr_backward(arr, 1, grads, L.options(), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    for name in ("A", "B", "K", "P", "x", "u", "lam", "chol"):
+        setattr(arr[0], name, 256)
+    with pytest.raises(L.LQRError) as e:      # upstream gradients missing
+        L.lqr_backward(arr, 1, grads, L.options(), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    grads[0].dl_dx = 256
+    grads[0].dl_du = 256
+    with pytest.raises(L.LQRError) as e:      # workspace too small
+        L.lqr_backward(arr, 1, grads, L.options(), 256, 8, 0)
+    assert e.value.status == L.ERR_WORKSPACE

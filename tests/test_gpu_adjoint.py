@@ -1,0 +1,118 @@
+"""GPU parity of the adjoint: lqr_backward and the LQRFunction autograd op
+against the CPU oracle's gradient, and against central finite differences
+(h = 1e-6) of the GPU forward solve itself.
+
+Loss throughout: l = sum_t |x_t|^2 + sum_t |u_t|^2 (so dl/dx = 2x, dl/du = 2u),
+each side computing its upstream gradient from its own forward solution.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import FP64_TOL, host, rel_err, to_device
+from synthetic import WORKLOADS, make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KEYS = ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")
+
+
+def gpu_grads(probs, segments=None):
+    import paper_1809_06360_amd as L
+    datas = [to_device(p) for p in probs]
+    outs, _ = L.solve_batched(datas, segments=segments, with_chol=True)
+    gx = [2.0 * o["x"] for o in outs]
+    gu = [2.0 * o["u"] for o in outs]
+    keys = tuple(k for k in KEYS if k != "S" or "S" in probs[0])
+    gs = L.backward(datas, outs, gx, gu, which=keys)
+    torch.cuda.synchronize()
+    return [host(g) for g in gs], [host(o) for o in outs]
+
+
+def oracle_grads(prob):
+    sol = oracle.solve(prob)
+    return oracle.backward(prob, sol, 2.0 * sol["x"], 2.0 * sol["u"])
+
+
+@pytest.mark.parametrize("dims", [
+    [(4, 2, 10, 1), (6, 3, 17, 4), (20, 7, 50, 7)],
+    [(33, 17, 40, 5), (1, 1, 6, 2)],
+])
+def test_backward_matches_oracle(dims):
+    probs = [make_instance(40 + i, 0, n, m, T) for i, (n, m, T, _) in enumerate(dims)]
+    got, _ = gpu_grads(probs, segments=[d[3] for d in dims])
+    for p, g, d in zip(probs, got, dims):
+        ref = oracle_grads(p)
+        for k in ("A", "B", "c", "Q", "q", "R", "r", "x0"):
+            assert rel_err(g[k], ref[k]) <= FP64_TOL, (d, k, rel_err(g[k], ref[k]))
+
+
+def test_backward_with_cross_term_matches_oracle():
+    probs = [make_instance(45, 0, 5, 3, 12, cross_term=True)]
+    got, _ = gpu_grads(probs, segments=[3])
+    ref = oracle_grads(probs[0])
+    for k in KEYS:
+        assert rel_err(got[0][k], ref[k]) <= FP64_TOL, k
+
+
+def test_lqr_function_on_differentiable_workload_sample():
+    """The 512-instance batch (n=16, m=8, T=128) through the autograd op in
+    one forward and one backward call; a fixed sample of instances is checked
+    against the oracle's gradient."""
+    import paper_1809_06360_amd as L
+    w = WORKLOADS["diff"]
+    probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
+    stack = {k: torch.stack([torch.from_numpy(p[k]) for p in probs]).cuda().requires_grad_(True)
+             for k in ("A", "B", "c", "Q", "q", "R", "r", "x0")}
+    x, u = L.LQRFunction.apply(*(stack[k] for k in ("A", "B", "c", "Q", "q", "R", "r", "x0")))
+    loss = (x * x).sum() + (u * u).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    for i in sorted(rng.choice(w.batch, size=12, replace=False)):
+        ref = oracle_grads(probs[i])
+        for k in ("A", "B", "c", "Q", "q", "R", "r", "x0"):
+            g = stack[k].grad[i].detach().cpu().numpy()
+            assert rel_err(g, ref[k]) <= FP64_TOL, (i, k)
+        sol = oracle.solve(probs[i])
+        assert rel_err(x[i].detach().cpu().numpy(), sol["x"]) <= FP64_TOL
+
+
+def test_backward_matches_central_differences_of_gpu_forward():
+    import paper_1809_06360_amd as L
+    prob = make_instance(46, 0, 4, 2, 10)
+    got, _ = gpu_grads([prob], segments=[2])
+    g = got[0]
+    h = 1e-6
+    rng = np.random.default_rng(3)
+
+    def loss(p):
+        out = L.solve(to_device(p), segments=2, with_lam=False)
+        torch.cuda.synchronize()
+        x, u = out["x"].cpu().numpy(), out["u"].cpu().numpy()
+        return float((x * x).sum() + (u * u).sum())
+
+    for key in ("A", "B", "c", "Q", "q", "R", "r", "x0"):
+        base = prob[key]
+        flat = base.reshape(-1)
+        for idx in rng.choice(flat.size, size=3, replace=False):
+            partner = None
+            if key in ("Q", "R"):
+                t, i, j = np.unravel_index(idx, base.shape)
+                if i != j:
+                    partner = np.ravel_multi_index((t, j, i), base.shape)
+            vals = []
+            for sgn in (+1.0, -1.0):
+                pert = dict(prob)
+                arr = flat.copy()
+                arr[idx] += sgn * h
+                if partner is not None:
+                    arr[partner] += sgn * h
+                pert[key] = arr.reshape(base.shape)
+                vals.append(loss(pert))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = g[key].reshape(-1)[idx] + (g[key].reshape(-1)[partner] if partner is not None else 0.0)
+            assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (key, idx, fd, an)

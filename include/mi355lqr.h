@@ -82,8 +82,12 @@ typedef enum {
  *                             fail, the largest such t is reported. The
  *                             instance's outputs are then NaN from that stage on.
  *   LQR_INFO_COUPLING + j     the linking system at segment boundary j had a
- *                             zero or non-finite pivot.                        */
+ *                             zero or non-finite pivot.
+ *   LQR_INFO_QUEUE            internal error of the persistent batched launch:
+ *                             a task waited about ten seconds for a dependency
+ *                             and gave up (outputs invalid).                   */
 #define LQR_INFO_COUPLING 0x40000000
+#define LQR_INFO_QUEUE 0x20000000
 
 /* One LQR instance. */
 typedef struct {
@@ -111,10 +115,15 @@ typedef struct {
     int32_t *info;         /* [1] device int32, see the info codes above          (required) */
 } lqr_problem_t;
 
+/* Option flags (lqr_options_t.flags). */
+#define LQR_FLAG_PHASED 0x1u   /* lqr_solve_batched: run the parallel algorithm as three
+                                  launches, one per phase, instead of one persistent
+                                  launch (same results; for comparison and timing) */
+
 typedef struct {
     lqr_precision_t precision;
     lqr_algo_t algo;
-    uint32_t flags;        /* must be 0 */
+    uint32_t flags;        /* 0 or LQR_FLAG_PHASED; other bits are invalid */
 } lqr_options_t;
 
 /* Upstream gradients and gradient outputs of lqr_backward (device pointers). */
@@ -150,13 +159,34 @@ lqr_status_t lqr_solve(const lqr_problem_t *prob, const lqr_options_t *opts,
 lqr_status_t lqr_solve_phase(const lqr_problem_t *prob, const lqr_options_t *opts, int32_t phase,
                              void *ws, size_t ws_bytes, void *stream);
 
-/* Solve `batch` independent instances of possibly different n, m, T in one
- * launch sequence. The execution plan (per-instance segment counts and the
- * work-item table) is built on the host and copied into the workspace; when a
- * call is made while `stream` is being captured into a HIP graph, the plan for
- * exactly these descriptors must already be in this workspace from an earlier,
- * uncaptured call (else LQR_ERR_INVALID_ARG), and the call then only launches
- * kernels. */
+/* Segment counts the planner picks for these instances (probs: HOST array;
+ * only n, m, T and segments are read; instances with segments > 0 keep theirs)
+ * and, if est_us is not NULL, the predicted makespan in microseconds of the
+ * persistent batched launch (0 for LQR_ALGO_SERIAL). segments: HOST int32
+ * array of `batch` entries. The planner picks every J_i of a batch together:
+ * it minimises a bound on the batch's makespan on the device's resident
+ * workgroups, max(total work / slots, longest instance critical path), under
+ * a per-stage cost model of the kernels measured on MI355X, then checks the
+ * best few candidates with a list-scheduling simulation (Sec. II-A fixes the
+ * split, not how many segments to use; the choice trades the longer segment
+ * sweeps of a small J against the serial linking chain of a large one). */
+lqr_status_t lqr_plan_segments(const lqr_problem_t *probs, int32_t batch,
+                               const lqr_options_t *opts, int32_t *segments, double *est_us);
+
+/* Solve `batch` independent instances of possibly different n, m, T.
+ * With LQR_ALGO_PARALLEL (and no LQR_FLAG_PHASED) this is ONE persistent
+ * launch (after a small kernel that clears its counters): resident
+ * workgroups take tasks -- segment sweeps, linking solves, rebuilds -- from a
+ * queue in an order fixed by the planner, and per-instance counters in the
+ * workspace make each linking solve wait for its instance's sweeps and each
+ * rebuild for its linking solve. With LQR_ALGO_SERIAL it is one workgroup per
+ * instance running the plain recursion. The execution plan (segment counts,
+ * descriptor and task tables) is built on the host and copied into the
+ * workspace; when a call is made while `stream` is being captured into a HIP
+ * graph, the plan for exactly these descriptors must already be in this
+ * workspace from an earlier, uncaptured call (else LQR_ERR_INVALID_ARG), and
+ * the call then only launches kernels (no memset nodes: the counters are
+ * cleared by a kernel, so graph replays are valid). */
 lqr_status_t lqr_solve_batched(const lqr_problem_t *probs, int32_t batch,
                                const lqr_options_t *opts, void *ws, size_t ws_bytes,
                                void *stream);

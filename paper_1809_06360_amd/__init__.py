@@ -17,10 +17,11 @@ import os
 
 __all__ = [
     "LIB_PATH", "library", "LqrProblem", "LqrOptions", "LqrGrad",
-    "lqr_workspace_size", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
-    "solve", "solve_batched", "LQRError",
+    "lqr_workspace_size", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched",
+    "lqr_backward", "lqr_status_string",
+    "solve", "solve_batched", "plan_segments", "backward", "LQRError",
     "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
-    "INFO_COUPLING",
+    "INFO_COUPLING", "FLAG_PHASED",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi355lqr.so")
@@ -30,6 +31,8 @@ ERR_NONFINITE, ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = 4, 5, 6, 7
 PREC_FP64, PREC_MIXED, PREC_FP32 = 0, 1, 2
 ALGO_PARALLEL, ALGO_SERIAL = 0, 1
 INFO_COUPLING = 0x40000000
+INFO_QUEUE = 0x20000000
+FLAG_PHASED = 0x1
 
 _vp = ctypes.c_void_p
 
@@ -50,8 +53,8 @@ class LqrGrad(ctypes.Structure):
                                          "dR", "dr", "dS", "dx0")]
 
 
-EXPORTS = ("lqr_workspace_size", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward",
-           "lqr_status_string")
+EXPORTS = ("lqr_workspace_size", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase",
+           "lqr_solve_batched", "lqr_backward", "lqr_status_string")
 
 _lib = None
 
@@ -73,6 +76,9 @@ def library():
         P = ctypes.POINTER
         lib.lqr_workspace_size.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), P(ctypes.c_size_t)]
         lib.lqr_workspace_size.restype = ctypes.c_int
+        lib.lqr_plan_segments.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), P(ctypes.c_int32),
+                                          P(ctypes.c_double)]
+        lib.lqr_plan_segments.restype = ctypes.c_int
         lib.lqr_solve.argtypes = [P(LqrProblem), P(LqrOptions), _vp, ctypes.c_size_t, _vp]
         lib.lqr_solve.restype = ctypes.c_int
         lib.lqr_solve_phase.argtypes = [P(LqrProblem), P(LqrOptions), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
@@ -102,6 +108,17 @@ def lqr_workspace_size(probs, batch: int, opts: LqrOptions) -> int:
     if st != SUCCESS:
         raise LQRError(st, "lqr_workspace_size")
     return int(out.value)
+
+
+def lqr_plan_segments(probs, batch: int, opts: LqrOptions):
+    """Per-instance segment counts the planner picks, and the predicted
+    makespan (microseconds) of the persistent batched launch."""
+    segs = (ctypes.c_int32 * int(batch))()
+    est = ctypes.c_double(0.0)
+    st = library().lqr_plan_segments(probs, int(batch), ctypes.byref(opts), segs, ctypes.byref(est))
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_plan_segments")
+    return list(segs), float(est.value)
 
 
 def lqr_solve(prob: LqrProblem, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:
@@ -137,8 +154,17 @@ _ALGO = {"parallel": ALGO_PARALLEL, "serial": ALGO_SERIAL}
 INPUTS = ("A", "B", "c", "Q", "q", "R", "r", "x0")
 
 
-def options(precision: str = "fp64", algo: str = "parallel") -> LqrOptions:
-    return LqrOptions(_PREC[precision], _ALGO[algo], 0)
+def options(precision: str = "fp64", algo: str = "parallel", phased: bool = False) -> LqrOptions:
+    return LqrOptions(_PREC[precision], _ALGO[algo], FLAG_PHASED if phased else 0)
+
+
+def plan_segments(dims, segments=None, algo: str = "parallel"):
+    """Planner's segment counts for instances of the given (n, m, T) and its
+    predicted makespan in microseconds (host only, no device needed)."""
+    arr = (LqrProblem * len(dims))()
+    for i, (n, m, T) in enumerate(dims):
+        arr[i] = LqrProblem(int(n), int(m), int(T), 0 if segments is None else int(segments[i]))
+    return lqr_plan_segments(arr, len(dims), options("fp64", algo))
 
 
 def _ptr(t):
@@ -219,10 +245,11 @@ def solve(data: dict, segments: int = 0, precision: str = "fp64", algo: str = "p
 
 def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "parallel",
                   with_P: bool = True, with_lam: bool = True, with_chol: bool = False,
-                  workspace=None, stream=None, outputs=None):
+                  workspace=None, stream=None, outputs=None, phased: bool = False):
     """Solve a list of instances (dicts of device tensors, possibly different
     n, m, T) with one batched call. ``segments``: None (planner) or a list of
-    per-instance segment counts. Returns (list of output dicts, workspace)."""
+    per-instance segment counts. ``phased``: three launches instead of the
+    persistent one. Returns (list of output dicts, workspace)."""
     import torch
     dtype = torch.float32 if precision == "fp32" else torch.float64
     device = datas[0]["A"].device
@@ -234,7 +261,7 @@ def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "pa
         out = outputs[i] if outputs is not None else _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol)
         outs.append(out)
         arr[i] = _problem(data, out, 0 if segments is None else segments[i])
-    opts = options(precision, algo)
+    opts = options(precision, algo, phased)
     nbytes = lqr_workspace_size(arr, batch, opts)
     ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
     s = (stream or torch.cuda.current_stream(device)).cuda_stream

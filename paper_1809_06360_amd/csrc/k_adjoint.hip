@@ -190,8 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_grad(const AdjDesc* descs,
 
 hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, int nblocks,
                           size_t lds, hipStream_t stream) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_adjoint_solve,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = ensure_dynamic_lds((const void*)k_adjoint_solve, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_solve, dim3(ninst), dim3(kThreads), lds, stream, descs);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -1,0 +1,7 @@
+// Persistent batched kernel, register width 24 (see k_persistent.h).
+#include "k_persistent.h"
+
+namespace lqr {
+LQR_PERSISTENT_INST(24, false)
+LQR_PERSISTENT_INST(24, true)
+}  // namespace lqr

@@ -25,7 +25,7 @@ struct k_serial_ref {
 hipError_t launch_k_serial(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
                    unsigned grid, int width, bool mf, size_t lds, hipStream_t stream) {
   return with_variant<k_serial_ref>(width, mf, [&](auto k) -> hipError_t {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_dynamic_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, stream, single, descs, items);
     return hipGetLastError();

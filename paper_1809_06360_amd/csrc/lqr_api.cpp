@@ -14,6 +14,7 @@
 #include "lqr_kernels.h"
 #include "lqr_launch.h"
 #include "lqr_layout.h"
+#include "lqr_tuner.h"
 #include "mi355lqr.h"
 
 namespace lqr {
@@ -44,24 +45,14 @@ size_t device_lds_bytes() {
   return bytes;
 }
 
-// Compute units of an MI355X; the planner sizes segment counts against it.
+// Compute units of an MI355X; the planner sizes batches against it.
 constexpr int kComputeUnits = 256;
 
-// Segment count for one instance when the caller leaves it to the planner.
-// Balances the per-segment sweeps (about T/J stages each, run concurrently)
-// against the linking solve (J-1 serially dependent boundary steps), i.e.
-// minimises T/J * c_sweep + J * c_link with c_link/c_sweep ~ 1/4 for the
-// sweep kernels here, giving J ~ 2 sqrt(T); capped so the instances of a
-// batch together do not ask for more than ~2 workgroups per compute unit.
-int plan_segments(int n, int m, int T, int batch, size_t lds_max, int mw, int nw) {
-  if (sweep_lds(n, m, true, mw) > lds_max || couple_lds(n, nw) > lds_max ||
-      !sweep_fits_regs(n, m, true) ||
-      n > 64)
-    return 1;
-  int J = (int)std::lround(2.0 * std::sqrt((double)T));
-  const int cap = std::max(1, 2 * kComputeUnits / std::max(1, batch));
-  J = std::min(J, cap);
-  return std::max(1, std::min(J, T));
+// Whether an instance can be split into segments: the dual sweep and the
+// linking solve must fit the kernels' register and LDS budgets.
+bool can_split(int n, int m, int mw, int nw) {
+  return n <= 64 && 2 * n + 1 <= 256 && sweep_fits_regs(n, m, true) &&
+         sweep_lds(n, m, true, mw) <= kLdsGfx950 && couple_lds(n, nw) <= kLdsGfx950;
 }
 
 struct InstPlan {
@@ -70,20 +61,27 @@ struct InstPlan {
   size_t ws_bytes;
 };
 
+// Workspace layout of a call: descriptor table | phase-1/3 work items (phased
+// launches) | persistent task table | synchronisation words | per-instance
+// scratch. The first three (up to sync_off) form the uploaded plan.
 struct BatchPlan {
   std::vector<InstPlan> inst;
-  size_t table_bytes = 0;  // descriptor table + work items, at the workspace base
+  std::vector<TaskItem> tasks;  // persistent launch order (parallel algorithm)
+  double est_us = 0.0;          // predicted makespan of the persistent launch
+  size_t items_off = 0, tasks_off = 0, sync_off = 0;
+  size_t table_bytes = 0;       // = sync_off
   size_t total_bytes = 0;
   int nitems = 0;
   int max_n = 1, max_m = 1;
-  size_t lds1 = 0, lds2 = 0, lds3 = 0, lds_serial = 0;
+  size_t lds1 = 0, lds2 = 0, lds3 = 0, lds_serial = 0, lds_persist = 0;
 };
 
 bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL; }
+bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
-  if (o->flags != 0) return LQR_ERR_INVALID_ARG;
+  if (o->flags & ~(uint32_t)LQR_FLAG_PHASED) return LQR_ERR_INVALID_ARG;
   if (o->algo != LQR_ALGO_PARALLEL && o->algo != LQR_ALGO_SERIAL) return LQR_ERR_INVALID_ARG;
   if (o->precision != LQR_PREC_FP64 && o->precision != LQR_PREC_MIXED &&
       o->precision != LQR_PREC_FP32)
@@ -105,15 +103,20 @@ lqr_status_t check_pointers(const lqr_problem_t& p) {
   return LQR_SUCCESS;
 }
 
-lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
-                       BatchPlan* plan) {
-  if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
+// Resident workgroups the tuner plans for: up to two per compute unit, as the
+// LDS footprint allows.
+int planned_slots(size_t lds) {
+  const size_t per_cu = std::max<size_t>(1, std::min<size_t>(2, kLdsGfx950 / std::max<size_t>(lds, 1)));
+  return (int)per_cu * kComputeUnits;
+}
+
+lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
+                        BatchPlan* plan) {
   lqr_status_t st = check_options(opts);
   if (st != LQR_SUCCESS) return st;
   const size_t lds_max = kLdsGfx950;
   const bool serial = is_serial(opts);
   plan->inst.resize(batch);
-  int items = 0;
   // The batch's largest dimensions pick the kernel variants, whose register
   // widths fix the LDS layouts; segment counts are planned against them.
   for (int i = 0; i < batch; ++i) {
@@ -122,35 +125,52 @@ lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_
     plan->max_n = std::max(plan->max_n, p.n);
     plan->max_m = std::max(plan->max_m, p.m);
   }
-  const int mw = pad_rows(plan->max_m), nw = pad_rows(plan->max_n);
+  const int mw = pad_rows(plan->max_m);
+  const bool mf = plan->max_n >= kMfmaMinN;
+  // linking-solve width: that of the phased kernel or of the persistent one
+  const int nw = std::max(pad_rows(plan->max_n), persist_nw(mf));
+  std::vector<TuneInst> tin(batch);
+  size_t lds_guess = 0;
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
-    const int J = serial ? 1
-                         : (p.segments > 0 ? p.segments
-                                           : plan_segments(p.n, p.m, p.T, batch, lds_max, mw, nw));
-    plan->inst[i].J = J;
-    items += J;
+    const bool split = !serial && can_split(p.n, p.m, mw, nw);
+    if (p.segments > 1 && !split && !serial) return LQR_ERR_UNSUPPORTED;
+    tin[i] = TuneInst{p.n, p.m, p.T, serial ? 1 : p.segments, split};
+    lds_guess = std::max(lds_guess, sweep_lds(p.n, p.m, split, mw));
+    if (split) lds_guess = std::max(lds_guess, couple_lds(p.n, nw));
+  }
+  std::vector<int> J = tune_segments(tin, mw, mf, planned_slots(lds_guess));
+  int items = 0;
+  for (int i = 0; i < batch; ++i) {
+    plan->inst[i].J = J[i];
+    items += J[i];
   }
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
-    const int J = plan->inst[i].J;
+    const int Ji = J[i];
     const size_t plain = sweep_lds(p.n, p.m, false, mw);
     if (plain > lds_max || !sweep_fits_regs(p.n, p.m, false)) return LQR_ERR_UNSUPPORTED;
-    if (J > 1 && (sweep_lds(p.n, p.m, true, mw) > lds_max || couple_lds(p.n, nw) > lds_max ||
-                  !sweep_fits_regs(p.n, p.m, true) || p.n > 64 || 2 * p.n + 1 > 256))
-      return LQR_ERR_UNSUPPORTED;
     plan->lds_serial = std::max(plan->lds_serial, std::max(plain, rollout_lds(p.n, p.m)));
-    plan->lds1 = std::max(plan->lds1, J > 1 ? sweep_lds(p.n, p.m, true, mw) : plain);
-    plan->lds2 = std::max(plan->lds2, couple_lds(p.n, nw));
+    plan->lds1 = std::max(plan->lds1, Ji > 1 ? sweep_lds(p.n, p.m, true, mw) : plain);
+    plan->lds2 = std::max(plan->lds2, couple_lds(p.n, pad_rows(plan->max_n)));
     plan->lds3 = std::max(plan->lds3, std::max(plain, rollout_lds(p.n, p.m)));
+    if (!serial) plan->lds_persist = std::max(plan->lds_persist, couple_lds(p.n, persist_nw(mf)));
+  }
+  if (!serial) {
+    plan->lds_persist = std::max(plan->lds_persist, std::max(plan->lds1, plan->lds3));
+    if (plan->lds_persist + 32 > lds_max) return LQR_ERR_UNSUPPORTED;
+    plan->tasks = order_tasks(tin, J, mw, mf, planned_slots(plan->lds_persist), &plan->est_us);
   }
   plan->nitems = items;
-  plan->table_bytes = align_up(sizeof(InstDesc) * (size_t)batch) + align_up(sizeof(WorkItem) * (size_t)items);
-  size_t off = plan->table_bytes;
+  plan->items_off = align_up(sizeof(InstDesc) * (size_t)batch);
+  plan->tasks_off = plan->items_off + align_up(sizeof(WorkItem) * (size_t)items);
+  plan->sync_off = plan->tasks_off + align_up(sizeof(TaskItem) * plan->tasks.size());
+  plan->table_bytes = plan->sync_off;
+  size_t off = plan->sync_off + align_up(sizeof(int32_t) * sync_words(batch));
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
-    const int J = plan->inst[i].J;
-    const size_t bytes = align_up(ws_doubles(p.n, J) * sizeof(double)) + align_up(sizeof(int32_t) * J);
+    const int Ji = J[i];
+    const size_t bytes = align_up(ws_doubles(p.n, Ji) * sizeof(double)) + align_up(sizeof(int32_t) * Ji);
     plan->inst[i].ws_off = off;
     plan->inst[i].ws_bytes = bytes;
     off += bytes;
@@ -159,9 +179,48 @@ lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_
   return LQR_SUCCESS;
 }
 
+// Plans are cached by (options, per-instance n, m, T, segments): the tuner's
+// search and the task ordering run once per distinct batch shape.
+std::mutex g_cache_mu;
+std::map<std::vector<int32_t>, BatchPlan> g_cache;
+
+lqr_status_t make_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
+                       BatchPlan* plan) {
+  if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
+  std::vector<int32_t> key;
+  key.reserve(4 + 4 * (size_t)batch);
+  key.push_back(batch);
+  key.push_back(opts ? (int32_t)opts->precision : 0);
+  key.push_back(opts ? (int32_t)opts->algo : 0);
+  key.push_back(opts ? (int32_t)opts->flags : 0);
+  for (int i = 0; i < batch; ++i) {
+    key.push_back(probs[i].n);
+    key.push_back(probs[i].m);
+    key.push_back(probs[i].T);
+    key.push_back(probs[i].segments);
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *plan = it->second;
+      return LQR_SUCCESS;
+    }
+  }
+  BatchPlan fresh;
+  lqr_status_t st = build_plan(probs, batch, opts, &fresh);
+  if (st != LQR_SUCCESS) return st;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  if (g_cache.size() >= 64) g_cache.clear();
+  g_cache[key] = fresh;
+  *plan = fresh;
+  return LQR_SUCCESS;
+}
+
 lqr_status_t check_device(const BatchPlan& plan) {
   const size_t lim = device_lds_bytes();
-  const size_t need = std::max(std::max(plan.lds1, plan.lds2), std::max(plan.lds3, plan.lds_serial));
+  const size_t need = std::max(std::max(plan.lds1, plan.lds2),
+                               std::max(std::max(plan.lds3, plan.lds_serial), plan.lds_persist + 32));
   return need <= lim ? LQR_SUCCESS : LQR_ERR_UNSUPPORTED;
 }
 
@@ -316,6 +375,21 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
   }
 }
 
+lqr_status_t lqr_plan_segments(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
+                               int32_t* segments, double* est_us) {
+  try {
+    if (!segments) return LQR_ERR_INVALID_ARG;
+    BatchPlan plan;
+    lqr_status_t st = make_plan(probs, batch, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    for (int i = 0; i < batch; ++i) segments[i] = plan.inst[i].J;
+    if (est_us) *est_us = plan.est_us;
+    return LQR_SUCCESS;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
 lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
                                void* ws, size_t ws_bytes, void* stream) {
   try {
@@ -330,11 +404,12 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     char* base = static_cast<char*>(ws);
     const bool serial = is_serial(opts);
 
-    // Host image of the table: descriptors, then (instance, segment) items
-    // ordered with the longest segments first.
+    // Host image of the plan: descriptors; (instance, segment) items of the
+    // phased launches, longest segments first; the persistent task order.
     std::vector<char> table(plan.table_bytes, 0);
     InstDesc* descs = reinterpret_cast<InstDesc*>(table.data());
-    WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + align_up(sizeof(InstDesc) * batch));
+    WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + plan.items_off);
+    TaskItem* tasks = reinterpret_cast<TaskItem*>(table.data() + plan.tasks_off);
     std::vector<std::pair<double, WorkItem>> order;
     order.reserve(plan.nitems);
     for (int i = 0; i < batch; ++i) {
@@ -352,6 +427,7 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
                        return a.first > b.first;
                      });
     for (int i = 0; i < plan.nitems; ++i) items[i] = order[i].second;
+    std::copy(plan.tasks.begin(), plan.tasks.end(), tasks);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -369,11 +445,18 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
       }
     }
     const InstDesc* ddesc = reinterpret_cast<const InstDesc*>(base);
-    const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + align_up(sizeof(InstDesc) * batch));
-    hipError_t e = serial ? launch_serial_batched(ddesc, batch, plan.max_n, plan.max_m,
-                                                  plan.lds_serial, s)
-                          : launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n,
-                                                    plan.max_m, plan.lds1, plan.lds2, plan.lds3, s);
+    const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + plan.items_off);
+    const TaskItem* dtasks = reinterpret_cast<const TaskItem*>(base + plan.tasks_off);
+    int32_t* dsync = reinterpret_cast<int32_t*>(base + plan.sync_off);
+    hipError_t e;
+    if (serial)
+      e = launch_serial_batched(ddesc, batch, plan.max_n, plan.max_m, plan.lds_serial, s);
+    else if (is_phased(opts))
+      e = launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n, plan.max_m,
+                                  plan.lds1, plan.lds2, plan.lds3, s);
+    else
+      e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync, plan.max_n,
+                            plan.max_m, plan.lds_persist, nullptr, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;

@@ -1,10 +1,28 @@
 // Launch sequences of the solver (host code).
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "lqr_kernels.h"
 #include "lqr_launch.h"
 
 namespace lqr {
+
+hipError_t ensure_dynamic_lds(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[{dev, kernel}];
+  if (have >= lds) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) have = lds;
+  return e;
+}
 
 static bool use_mfma(int n) { return n >= kMfmaMinN; }
 

@@ -7,6 +7,11 @@
 
 namespace lqr {
 
+// Raise the kernel's dynamic-LDS limit to at least `lds` bytes on the current
+// device (the runtime call is made once per kernel, device and size increase,
+// so launches under stream capture normally make none).
+hipError_t ensure_dynamic_lds(const void* kernel, size_t lds);
+
 // Call f with the kernel instantiation K<pad_rows(width), mf>.
 template <template <int, bool> class K, typename F>
 hipError_t with_variant(int width, bool mf, F f) {
@@ -30,6 +35,14 @@ hipError_t launch_k_phase3(const InstDesc& single, const InstDesc* descs, const 
                            unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
 hipError_t launch_k_serial(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
                            unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+
+// Persistent batched solve: clears the `sync` words, then launches one
+// workgroup per resident slot (occupancy x compute units, at most ntasks),
+// each draining the task queue. lds_items: LDS bytes the tasks need.
+// *grid_out (if not null) receives the grid size.
+hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int ntasks, int ninst,
+                             int32_t* sync, int max_n, int max_m, size_t lds_items,
+                             int* grid_out, hipStream_t stream);
 
 // Adjoint solve (one workgroup per instance) followed by the gradient
 // outer products (one workgroup per (instance, kAdjStages stages) block).

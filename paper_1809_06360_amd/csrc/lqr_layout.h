@@ -51,6 +51,22 @@ struct WorkItem {
   int32_t inst, seg;
 };
 
+// A task of the persistent batched launch: phase 1 (segment sweep), 2
+// (linking solve, seg unused) or 3 (rebuild and forward simulation) of one
+// (instance, segment). Tasks are taken from a queue in table order, which the
+// host makes a topological order of the dependencies
+//   every phase-1 task of an instance  ->  its phase-2 task  ->  its phase-3 tasks.
+struct TaskItem {
+  int32_t inst, seg, phase;
+};
+
+// Synchronisation words of a persistent launch (int32, zeroed before every
+// launch): the queue head, then per instance the number of finished phase-1
+// tasks, then per instance the finished flag of its phase-2 task.
+LQR_HD size_t sync_words(int ninst) { return 64 + 2 * (size_t)ninst; }
+constexpr int kSyncHead = 0;
+constexpr int kSyncDone1 = 64;  // the head sits alone in its 256-byte line
+
 // Segment j covers stages [seg_begin(j), seg_begin(j+1)); the first T mod J
 // segments are one stage longer.
 LQR_HD int seg_begin(int T, int J, int j) {
@@ -119,6 +135,10 @@ constexpr int kMfmaMinN = 32;
 // Linking solve: sPn n x n, spn n, sA1 n x n, sN mp x (2n+1) column-major
 // (mp = pad_rows(n) + 1), vectors, Gauss-Jordan exchange (3 pad + 2), pivots.
 LQR_HD size_t couple_lds(int n, int nw);
+
+// Register width of the linking solve inside the persistent kernel: one
+// width per product engine (MFMA variants serve n <= 64, VALU ones n < 32).
+LQR_HD constexpr int persist_nw(bool mf) { return mf ? 64 : 32; }
 
 // Forward simulation: x_t and x_{t+1} (n each), u_t (m).
 LQR_HD size_t rollout_lds(int n, int m) { return (2 * (size_t)n + m) * 8 + 64; }

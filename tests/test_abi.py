@@ -80,7 +80,7 @@ def test_workspace_size_rejects_bad_dimensions(n, m, T, J):
 
 def test_workspace_size_rejects_bad_options():
     opts = L.options()
-    opts.flags = 1
+    opts.flags = 2          # only LQR_FLAG_PHASED (1) is defined
     with pytest.raises(L.LQRError) as e:
         L.lqr_workspace_size(ctypes.byref(_prob()), 1, opts)
     assert e.value.status == L.ERR_INVALID_ARG
@@ -89,10 +89,12 @@ def test_workspace_size_rejects_bad_options():
 
 
 def test_workspace_size_is_machine_independent_and_monotone():
-    a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options())
+    (J,), _ = L.lqr_plan_segments(ctypes.byref(_prob(48, 24, 1024, 0)), 1, L.options())
+    assert 1 < J <= 1024
+    a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, J)), 1, L.options())
     b = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 0)), 1, L.options())
-    c = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 16)), 1, L.options())
-    assert a == b     # the planner picks 64 segments for T = 1024
+    c = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, max(1, J // 2))), 1, L.options())
+    assert a == b     # segments = 0 means the planner's choice
     assert c < a
     arr = (L.LqrProblem * 2)(_prob(8, 4, 64, 4), _prob(12, 3, 50, 7))
     both = L.lqr_workspace_size(arr, 2, L.options())
@@ -152,3 +154,27 @@ def test_backward_rejects_bad_arguments():
     with pytest.raises(L.LQRError) as e:      # workspace too small
         L.lqr_backward(arr, 1, grads, L.options(), 256, 8, 0)
     assert e.value.status == L.ERR_WORKSPACE
+
+
+def test_plan_segments_respects_fixed_counts_and_algorithm():
+    dims = [(4, 2, 64), (48, 24, 1024), (12, 3, 50), (60, 30, 400)]
+    segs, est = L.plan_segments(dims, segments=[4, 64, 0, 0])
+    assert segs[0] == 4 and segs[1] == 64
+    assert all(1 <= J <= T for J, (_, _, T) in zip(segs, dims))
+    assert est > 0
+    serial, est_s = L.plan_segments(dims, algo="serial")
+    assert serial == [1] * 4 and est_s == 0.0
+    again, est2 = L.plan_segments(dims, segments=[4, 64, 0, 0])
+    assert again == segs and est2 == est          # deterministic (and cached)
+    with pytest.raises(L.LQRError) as e:
+        L.plan_segments([(4, 2, 10)], segments=[11])
+    assert e.value.status == L.ERR_INVALID_ARG
+
+
+def test_planner_splits_long_single_instances_more_than_short_ones():
+    (j_long,), _ = L.plan_segments([(16, 8, 4096)])
+    (j_short,), _ = L.plan_segments([(16, 8, 64)])
+    assert j_long > j_short >= 1
+    # a batch that fills the device on its own needs no splitting
+    segs, _ = L.plan_segments([(16, 8, 128)] * 512)
+    assert set(segs) == {1}

@@ -1,0 +1,105 @@
+"""GPU parity of the persistent batched launch and of its graph capture.
+
+The persistent launch (one kernel draining a task queue) must give the
+oracle's results, the same results as the three-launch (phased) path, report
+numerical failures per instance, and give bitwise identical results when the
+call is captured into a graph and replayed with new input values.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import FP64_TOL, compare, host, to_device
+from synthetic import make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+OUTS = ("K", "k", "P", "p", "x", "u", "lam")
+
+
+def _batch(cfg, dims):
+    return [make_instance(cfg, i, n, m, T) for i, (n, m, T, _) in enumerate(dims)]
+
+
+def test_persistent_matches_oracle_and_phased_path():
+    import paper_1809_06360_amd as L
+    dims = [(4, 2, 64, 4), (20, 7, 50, 0), (33, 17, 70, 9), (1, 1, 5, 0), (48, 24, 128, 8),
+            (9, 9, 40, 1), (30, 5, 200, 0), (12, 12, 3, 3)]
+    probs = _batch(50, dims)
+    datas = [to_device(p) for p in probs]
+    segs = [d[3] for d in dims]
+    per, _ = L.solve_batched(datas, segments=segs)
+    pha, _ = L.solve_batched(datas, segments=segs, phased=True)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        a, b = host(per[i]), host(pha[i])
+        assert int(a["info"][0]) == 0 and int(b["info"][0]) == 0, i
+        compare(a, oracle.solve(p), label="persistent %d %s" % (i, dims[i]))
+        for k in OUTS:
+            assert np.array_equal(a[k], b[k]), (i, k)
+
+
+def test_persistent_reports_indefinite_stage_per_instance():
+    import paper_1809_06360_amd as L
+    dims = [(6, 3, 20, 4), (6, 3, 20, 1), (5, 2, 16, 4)]
+    probs = _batch(51, dims)
+    for p in probs[:2]:
+        p["R"][6] = -50.0 * np.eye(3)
+    outs, _ = L.solve_batched([to_device(p) for p in probs], segments=[d[3] for d in dims])
+    torch.cuda.synchronize()
+    assert int(outs[0]["info"][0]) == 7
+    assert int(outs[1]["info"][0]) == 7
+    assert int(outs[2]["info"][0]) == 0
+    compare(host(outs[2]), oracle.solve(probs[2]))
+
+
+def test_graph_replays_match_eager_calls():
+    """Capture one batched call into a graph; replay it three times, changing
+    x0 and q in place between replays (with eager work and synchronisation in
+    between), and compare every replay bitwise with an eager call on the same
+    inputs."""
+    import paper_1809_06360_amd as L
+    dims = [(16, 8, 96, 0), (40, 20, 160, 0), (7, 3, 33, 0), (24, 12, 64, 4)]
+    probs = _batch(52, dims)
+    datas = [to_device(p) for p in probs]
+    outs, ws = L.solve_batched(datas)                 # uncaptured: uploads the plan
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.solve_batched(datas, outputs=outs, workspace=ws)
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        for d in datas:
+            d["x0"].copy_(torch.from_numpy(rng.standard_normal(d["x0"].shape[0])))
+            d["q"].mul_(-0.5 if rep % 2 else 1.5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eager, _ = L.solve_batched(datas)
+        torch.cuda.synchronize()
+        for i in range(len(dims)):
+            a, b = host(outs[i]), host(eager[i])
+            assert int(a["info"][0]) == 0
+            for k in OUTS:
+                assert np.array_equal(a[k], b[k]), (rep, i, k)
+        if rep == 2:
+            cur = {k: v.cpu().numpy() for k, v in datas[1].items()}
+            compare(host(outs[1]), oracle.solve(cur), tol=FP64_TOL)
+
+
+def test_capture_without_resident_plan_is_rejected():
+    import paper_1809_06360_amd as L
+    probs = _batch(53, [(8, 4, 32, 0)])
+    datas = [to_device(p) for p in probs]
+    outs, ws = L.solve_batched(datas)
+    torch.cuda.synchronize()
+    fresh = torch.empty_like(ws)
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(L.LQRError) as e:
+        with torch.cuda.graph(g):
+            L.solve_batched(datas, outputs=outs, workspace=fresh)
+    assert e.value.status == L.ERR_INVALID_ARG
+    torch.cuda.synchronize()

@@ -129,7 +129,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="large", choices=["small", "large"])
+    ap.add_argument("--workload", default="large", choices=["small", "large", "batched"])
+    ap.add_argument("--no-batched-summary", action="store_true",
+                    help="skip the short batched-workload measurement added to the single-instance line")
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate budget of the oracle CPU-baseline sample (0 = skip)")
@@ -154,6 +156,10 @@ def main():
         from paper_1809_06360_amd import build as hip_build
         hip_build.build()
 
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, WORKLOADS["batched"])), flush=True)
+        return
+
     w = WORKLOADS[args.workload]
     (n, m, T), = w.dims
     J = w.segments
@@ -174,17 +180,11 @@ def main():
     def step():
         L.lqr_solve(prob, opts, ws.data_ptr(), ws_bytes, sh)
 
-    # correctness gate on the timed configuration
     step()
     torch.cuda.synchronize()
     info = int(out["info"].item())
+    gpu_out = {k: out[k].cpu().numpy() for k in ("K", "k", "P", "p", "x", "u", "lam")}
     rel = None
-    if args.cpu_seconds > 0:
-        import oracle
-        ref = oracle.solve(prob_np)
-        rel = {k: float(np.linalg.norm(out[k].cpu().numpy() - ref[k]) / np.linalg.norm(ref[k]))
-               for k in ("K", "k", "P", "p", "x", "u", "lam")}
-        log("max rel err vs oracle %.2e (info %d)" % (max(rel.values()), info))
 
     for _ in range(args.warmup):
         step()
@@ -253,7 +253,12 @@ def main():
 
     cpu = None
     if args.cpu_seconds > 0:
+        # CPU baseline: the oracle timed on the host; its first solution also
+        # gives the relative error of the timed GPU configuration
         import oracle
+        ref = oracle.solve(prob_np)
+        rel = {k: float(np.linalg.norm(gpu_out[k] - ref[k]) / np.linalg.norm(ref[k])) for k in gpu_out}
+        log("max rel err vs oracle %.2e (info %d)" % (max(rel.values()), info))
         t = time.perf_counter()
         oracle.solve(prob_np, with_lam=False)
         one = time.perf_counter() - t
@@ -293,7 +298,130 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if not args.no_batched_summary:
+        try:
+            bargs = argparse.Namespace(steps=5, warmup=2, serial_steps=2, cpu_seconds=0.0)
+            b = run_batched(bargs, WORKLOADS["batched"])
+            result["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "config", "phased",
+                                                   "serial_gpu", "speedup_vs_serial_gpu", "max_rel_err",
+                                                   "roofline")}
+        except Exception as exc:  # the headline line must still be printed
+            result["batched"] = {"error": repr(exc)}
     print(json.dumps(result), flush=True)
+
+
+def batch_flops(dims, segs):
+    tot = 0.0
+    for (n, m, T), J in zip(dims, segs):
+        f = kernel_flops(n, m, T, J)
+        tot += f[1] + f[2] + f[3] if J > 1 else f["serial"]
+    return tot
+
+
+def run_batched(args, w):
+    """The batched workload: all instances in one persistent launch captured
+    in a HIP graph (timed as graph replays), against the three-launch phased
+    path and the plain serial kernel on the same instances."""
+    import numpy as np
+    import torch
+
+    import paper_1809_06360_amd as L
+    from synthetic import make_instance
+
+    dev = torch.device("cuda:0")
+    log("batched workload %s: %d instances" % (w.name, w.batch))
+    probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
+    datas = [{k: torch.from_numpy(v).to(dev) for k, v in p.items()} for p in probs]
+    segs, est = L.plan_segments(w.dims)
+    outs, ws = L.solve_batched(datas)
+    torch.cuda.synchronize()
+    infos = [int(o["info"].item()) for o in outs]
+    keys = ("K", "k", "P", "p", "x", "u", "lam")
+    first = [{k: outs[i][k].cpu().numpy() for k in keys} for i in range(min(w.batch, 64))]
+    rel = None
+    stream = torch.cuda.current_stream(dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.solve_batched(datas, outputs=outs, workspace=ws)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    K = args.steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(K):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / K
+    kern = e0.elapsed_time(e1) / K
+    log("persistent graph: %.3f ms/step (events %.3f ms)" % (ms, kern))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ph_ms = timed(lambda: L.solve_batched(datas, outputs=outs, workspace=ws, phased=True), max(2, K // 2))
+    se_ms = timed(lambda: L.solve_batched(datas, outputs=outs, workspace=ws, algo="serial"),
+                  args.serial_steps)
+    log("phased %.3f ms/step, serial kernel %.3f ms/step" % (ph_ms, se_ms))
+    flops = batch_flops(w.dims, segs)
+    achieved = flops / (kern * 1e-3) / 1e12
+    cpu = None
+    if args.cpu_seconds > 0:
+        # CPU baseline: the oracle on the first instances of the batch, whose
+        # solutions also give the relative error of the GPU results
+        import oracle
+        t = time.perf_counter()
+        done, errs = 0, []
+        while done < w.batch and time.perf_counter() - t < args.cpu_seconds:
+            ref = oracle.solve(probs[done])
+            if done < len(first):
+                errs.append(max(float(np.linalg.norm(first[done][k] - ref[k]) / np.linalg.norm(ref[k]))
+                                for k in keys))
+            done += 1
+        dt = time.perf_counter() - t
+        rel = max(errs) if errs else None
+        cpu = {"value": done / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "the first %d instances of the batch, serial FP64 solves on one host core, %.1f s"
+                         % (done, dt)}
+    steps_total = sum(T for (_, _, T) in w.dims)
+    return {
+        "metric": METRIC,
+        "value": w.batch * 1e3 / ms,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": w.batch, "timesteps": steps_total,
+                   "segments": "autotuned (%d..%d, %d in total)" % (min(segs), max(segs), sum(segs)),
+                   "launch": "one persistent kernel, hipGraph replay", "predicted_ms": est / 1e3},
+        "timesteps_per_s": steps_total * 1e3 / ms,
+        "max_rel_err": rel,
+        "info_max": max(infos),
+        "phased": {"solves_per_s": w.batch * 1e3 / ph_ms, "ms_per_step": ph_ms},
+        "serial_gpu": {"solves_per_s": w.batch * 1e3 / se_ms, "ms_per_step": se_ms, "kernel": "k_serial"},
+        "speedup_vs_serial_gpu": se_ms / ms,
+        "roofline": {"kernel": "k_persistent", "bound": "alu", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "kernel_ms": kern},
+        "cpu_baseline": cpu,
+    }
 
 
 if __name__ == "__main__":

@@ -208,6 +208,26 @@ def main():
     log("timed %d steps: %.3f ms/step; kernels %s" % (K, ms_per_step,
                                                       {KERNEL_NAMES[p]: round(v, 4) for p, v in kern_ms.items()}))
 
+    # mixed precision (FP32 matrix-core bulk products, FP64 factorizations and
+    # linking solve) on the same inputs and segments
+    mout = {k: torch.empty_like(v) for k, v in out.items()}
+    mprob = L._problem(data, mout, J)
+    mopts = L.options("mixed", "parallel")
+    mws_bytes = L.lqr_workspace_size(ctypes.byref(mprob), 1, mopts)
+    mws = torch.empty(mws_bytes, dtype=torch.uint8, device=dev)
+    for _ in range(max(1, args.warmup)):
+        L.lqr_solve(mprob, mopts, mws.data_ptr(), mws_bytes, sh)
+    torch.cuda.synchronize()
+    me0, me1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    me0.record(stream)
+    for _ in range(K):
+        L.lqr_solve(mprob, mopts, mws.data_ptr(), mws_bytes, sh)
+    me1.record(stream)
+    torch.cuda.synchronize()
+    mixed_ms = me0.elapsed_time(me1) / K
+    mixed_out = {k: mout[k].cpu().numpy() for k in ("K", "k", "P", "p", "x", "u", "lam")}
+    log("mixed precision %.3f ms/solve" % mixed_ms)
+
     # plain serial Riccati kernel on the same inputs
     sopts = L.options("fp64", "serial")
     sprob = L._problem(data, out, 0)
@@ -252,13 +272,17 @@ def main():
     }
 
     cpu = None
+    mixed_rel = None
     if args.cpu_seconds > 0:
         # CPU baseline: the oracle timed on the host; its first solution also
         # gives the relative error of the timed GPU configuration
         import oracle
         ref = oracle.solve(prob_np)
         rel = {k: float(np.linalg.norm(gpu_out[k] - ref[k]) / np.linalg.norm(ref[k])) for k in gpu_out}
-        log("max rel err vs oracle %.2e (info %d)" % (max(rel.values()), info))
+        mixed_rel = {k: float(np.linalg.norm(mixed_out[k] - ref[k]) / np.linalg.norm(ref[k]))
+                     for k in mixed_out}
+        log("max rel err vs oracle %.2e (info %d); mixed %.2e" % (max(rel.values()), info,
+                                                                  max(mixed_rel.values())))
         t = time.perf_counter()
         oracle.solve(prob_np, with_lam=False)
         one = time.perf_counter() - t
@@ -295,6 +319,10 @@ def main():
         "serial_gpu": {"solves_per_s": 1e3 / serial_ms, "ms_per_solve": serial_ms,
                        "kernel": "k_serial"},
         "speedup_vs_serial_gpu": serial_ms / ms_per_step,
+        "mixed_precision": {"ms_per_solve": mixed_ms, "solves_per_s": 1e3 / mixed_ms,
+                            "rel_err": mixed_rel,
+                            "note": "same instance and segments; FP32 matrix-core bulk products "
+                                    "with FP32 accumulation, FP64 Cholesky, gains and linking solve"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -64,9 +64,15 @@ typedef enum {
 
 typedef enum {
     LQR_PREC_FP64 = 0,   /* everything in double */
-    LQR_PREC_MIXED = 1,  /* double I/O; bulk products in float on MFMA with float
-                            accumulation; factorizations and the linking solve in double */
-    LQR_PREC_FP32 = 2    /* everything in float */
+    LQR_PREC_MIXED = 1,  /* double I/O; the bulk products of the segment sweeps
+                            (P[B|A|c], B'P[B|A|c], A'PA, B'Gamma, Gamma and Psi updates)
+                            in float on matrix cores with float accumulation, their
+                            results widened to double; the input Hessian R + B'PB is
+                            assembled and Cholesky-factored in double, the gains and
+                            the linking solve are double. lqr_backward computes in
+                            double. */
+    LQR_PREC_FP32 = 2    /* everything in float: not supported by this library
+                            version (LQR_ERR_UNSUPPORTED) */
 } lqr_precision_t;
 
 typedef enum {

@@ -61,7 +61,7 @@ LQR_DEV bool wait_at_least(const int32_t* ctr, int target, int wave, int* sflag)
 
 // `sync` holds sync_words(ninst) int32 words, zero at launch. The dynamic LDS
 // is lds_items bytes for the tasks plus 16 bytes for the ticket broadcast.
-template <int MW, bool MF>
+template <int MW, int E>
 __global__ __launch_bounds__(kThreads) void k_persistent(const InstDesc* descs,
                                                          const TaskItem* tasks, int ntasks,
                                                          int ninst, int32_t* sync,
@@ -92,13 +92,13 @@ __global__ __launch_bounds__(kThreads) void k_persistent(const InstDesc* descs,
     const InstDesc d = descs[inst];
     bool gave_up = false;
     if (phase == 1) {
-      phase1_item<MW, MF>(d, w.seg, smem);
+      phase1_item<MW, E>(d, w.seg, smem);
     } else if (phase == 2) {
       gave_up = wait_at_least(done1 + inst, d.J, wave, sflag);
-      couple_item<persist_nw(MF), MF>(d, smem);
+      couple_item<persist_nw(E != kEngValu), fp64_engine(E)>(d, smem);
     } else {
       gave_up = wait_at_least(done2 + inst, 1, wave, sflag);
-      phase3_item<MW, MF>(d, w.seg, smem);
+      phase3_item<MW, E>(d, w.seg, smem);
     }
     if (gave_up && wave == 0)
       __hip_atomic_store(d.info, LQR_INFO_QUEUE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -114,13 +114,13 @@ __global__ __launch_bounds__(kThreads) void k_persistent(const InstDesc* descs,
   }
 }
 
-// Launch the <MW, MF> variant with one workgroup per resident slot
+// Launch the <MW, E> variant with one workgroup per resident slot
 // (occupancy x compute units, at most ntasks). `lds` includes the ticket slot.
-template <int MW, bool MF>
+template <int MW, int E>
 hipError_t launch_persistent_variant(const InstDesc* descs, const TaskItem* tasks, int ntasks,
                                      int ninst, int32_t* sync, unsigned lds_items, size_t lds,
                                      int cus, int* grid_out, hipStream_t stream) {
-  const void* k = (const void*)&k_persistent<MW, MF>;
+  const void* k = (const void*)&k_persistent<MW, E>;
   hipError_t e = ensure_dynamic_lds(k, lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -129,7 +129,7 @@ hipError_t launch_persistent_variant(const InstDesc* descs, const TaskItem* task
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const int grid = std::min(ntasks, per_cu * cus);
   if (grid_out) *grid_out = grid;
-  hipLaunchKernelGGL((k_persistent<MW, MF>), dim3(grid), dim3(kThreads), lds, stream, descs, tasks,
+  hipLaunchKernelGGL((k_persistent<MW, E>), dim3(grid), dim3(kThreads), lds, stream, descs, tasks,
                      ntasks, ninst, sync, lds_items);
   return hipGetLastError();
 }

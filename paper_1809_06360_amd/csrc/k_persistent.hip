@@ -4,7 +4,7 @@
 
 namespace lqr {
 
-#define LQR_DECL2(W) LQR_PERSISTENT_DECL(W, false) LQR_PERSISTENT_DECL(W, true)
+#define LQR_DECL2(W) LQR_PERSISTENT_DECL(W, 0) LQR_PERSISTENT_DECL(W, 1) LQR_PERSISTENT_DECL(W, 2)
 LQR_DECL2(8) LQR_DECL2(16) LQR_DECL2(24) LQR_DECL2(32) LQR_DECL2(48) LQR_DECL2(64)
 #undef LQR_DECL2
 
@@ -28,9 +28,8 @@ int device_cus() {
 }  // namespace
 
 hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int ntasks, int ninst,
-                             int32_t* sync, int max_n, int max_m, size_t lds_items,
+                             int32_t* sync, int max_m, int eng, size_t lds_items,
                              int* grid_out, hipStream_t stream) {
-  const bool mf = max_n >= kMfmaMinN;
   const int words = (int)sync_words(ninst);
   const int cblocks = std::min(64, (words + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_clear_sync, dim3(cblocks), dim3(kThreads), 0, stream, sync, words);
@@ -43,10 +42,12 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
   switch (pad_rows(max_m)) {
 #define LQR_CASE(W)                                                                            \
   case W:                                                                                      \
-    return mf ? launch_persistent_variant<W, true>(descs, tasks, ntasks, ninst, sync, li, lds,   \
-                                                   cus, grid_out, stream)                      \
-              : launch_persistent_variant<W, false>(descs, tasks, ntasks, ninst, sync, li, lds,  \
-                                                    cus, grid_out, stream);
+    return eng == 2   ? launch_persistent_variant<W, 2>(descs, tasks, ntasks, ninst, sync, li, lds, \
+                                                        cus, grid_out, stream)                    \
+           : eng == 1 ? launch_persistent_variant<W, 1>(descs, tasks, ntasks, ninst, sync, li, lds, \
+                                                        cus, grid_out, stream)                    \
+                      : launch_persistent_variant<W, 0>(descs, tasks, ntasks, ninst, sync, li, lds, \
+                                                        cus, grid_out, stream);
     LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
 #undef LQR_CASE
   }

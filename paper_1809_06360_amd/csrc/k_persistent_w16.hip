@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(16, false)
-LQR_PERSISTENT_INST(16, true)
+LQR_PERSISTENT_INST(16, 0)
+LQR_PERSISTENT_INST(16, 1)
+LQR_PERSISTENT_INST(16, 2)
 }  // namespace lqr

@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(24, false)
-LQR_PERSISTENT_INST(24, true)
+LQR_PERSISTENT_INST(24, 0)
+LQR_PERSISTENT_INST(24, 1)
+LQR_PERSISTENT_INST(24, 2)
 }  // namespace lqr

@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(32, false)
-LQR_PERSISTENT_INST(32, true)
+LQR_PERSISTENT_INST(32, 0)
+LQR_PERSISTENT_INST(32, 1)
+LQR_PERSISTENT_INST(32, 2)
 }  // namespace lqr

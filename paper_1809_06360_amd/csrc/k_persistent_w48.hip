@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(48, false)
-LQR_PERSISTENT_INST(48, true)
+LQR_PERSISTENT_INST(48, 0)
+LQR_PERSISTENT_INST(48, 1)
+LQR_PERSISTENT_INST(48, 2)
 }  // namespace lqr

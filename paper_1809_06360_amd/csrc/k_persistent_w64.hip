@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(64, false)
-LQR_PERSISTENT_INST(64, true)
+LQR_PERSISTENT_INST(64, 0)
+LQR_PERSISTENT_INST(64, 1)
+LQR_PERSISTENT_INST(64, 2)
 }  // namespace lqr

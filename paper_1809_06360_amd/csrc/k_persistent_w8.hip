@@ -2,6 +2,7 @@
 #include "k_persistent.h"
 
 namespace lqr {
-LQR_PERSISTENT_INST(8, false)
-LQR_PERSISTENT_INST(8, true)
+LQR_PERSISTENT_INST(8, 0)
+LQR_PERSISTENT_INST(8, 1)
+LQR_PERSISTENT_INST(8, 2)
 }  // namespace lqr

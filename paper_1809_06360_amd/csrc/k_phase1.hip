@@ -6,26 +6,27 @@
 namespace lqr {
 
 // Instantiated per register width MW (8..64, the padded input dimension m held in
-// registers by the elimination) and per product engine MF (matrix cores for
-// n >= 32), so that each launch runs one compact variant.
-template <int MW, bool MF>
+// registers by the elimination) and per product engine E (FP64 vector ALUs,
+// FP64 or FP32 matrix cores; see pgemm_sub), so that each launch runs one
+// compact variant.
+template <int MW, int E>
 __global__ __launch_bounds__(kThreads) void k_phase1(InstDesc single, const InstDesc* descs,
                                                      const WorkItem* items) {
   extern __shared__ double smem[];
   InstDesc d;
   int seg;
   select_item(single, descs, items, d, seg);
-  phase1_item<MW, MF>(d, seg, smem);
+  phase1_item<MW, E>(d, seg, smem);
 }
 
-template <int W, bool M>
+template <int W, int M>
 struct k_phase1_ref {
   static auto fn() { return &k_phase1<W, M>; }
 };
 
 hipError_t launch_k_phase1(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
-                   unsigned grid, int width, bool mf, size_t lds, hipStream_t stream) {
-  return with_variant<k_phase1_ref>(width, mf, [&](auto k) -> hipError_t {
+                   unsigned grid, int width, int eng, size_t lds, hipStream_t stream) {
+  return with_variant<k_phase1_ref>(width, eng, [&](auto k) -> hipError_t {
     hipError_t e = ensure_dynamic_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, stream, single, descs, items);

@@ -78,6 +78,7 @@ struct BatchPlan {
 
 bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL; }
 bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
+bool is_mixed(const lqr_options_t* o) { return o && o->precision == LQR_PREC_MIXED; }
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
@@ -86,7 +87,7 @@ lqr_status_t check_options(const lqr_options_t* o) {
   if (o->precision != LQR_PREC_FP64 && o->precision != LQR_PREC_MIXED &&
       o->precision != LQR_PREC_FP32)
     return LQR_ERR_INVALID_ARG;
-  if (o->precision != LQR_PREC_FP64) return LQR_ERR_UNSUPPORTED;
+  if (o->precision == LQR_PREC_FP32) return LQR_ERR_UNSUPPORTED;
   return LQR_SUCCESS;
 }
 
@@ -126,7 +127,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     plan->max_m = std::max(plan->max_m, p.m);
   }
   const int mw = pad_rows(plan->max_m);
-  const bool mf = plan->max_n >= kMfmaMinN;
+  const int eng = launch_engine(plan->max_n, is_mixed(opts));
+  const bool mf = eng != 0;
   // linking-solve width: that of the phased kernel or of the persistent one
   const int nw = std::max(pad_rows(plan->max_n), persist_nw(mf));
   std::vector<TuneInst> tin(batch);
@@ -341,8 +343,9 @@ lqr_status_t lqr_solve(const lqr_problem_t* prob, const lqr_options_t* opts, voi
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
     const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = is_serial(opts) ? launch_serial(d, plan.lds_serial, s)
-                                   : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, s);
+    const int eng = launch_engine(plan.max_n, is_mixed(opts));
+    hipError_t e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
+                                   : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;
@@ -363,11 +366,12 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
     const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
+    const int eng = launch_engine(plan.max_n, is_mixed(opts));
     if (is_serial(opts)) {
-      if (phase == 1) e = launch_serial(d, plan.lds_serial, s);
+      if (phase == 1) e = launch_serial(d, plan.lds_serial, eng, s);
     } else {
       const size_t lds = phase == 1 ? plan.lds1 : phase == 2 ? plan.lds2 : plan.lds3;
-      e = launch_phase(d, phase, lds, s);
+      e = launch_phase(d, phase, lds, eng, s);
     }
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
@@ -449,14 +453,15 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     const TaskItem* dtasks = reinterpret_cast<const TaskItem*>(base + plan.tasks_off);
     int32_t* dsync = reinterpret_cast<int32_t*>(base + plan.sync_off);
     hipError_t e;
+    const int eng = launch_engine(plan.max_n, is_mixed(opts));
     if (serial)
-      e = launch_serial_batched(ddesc, batch, plan.max_n, plan.max_m, plan.lds_serial, s);
+      e = launch_serial_batched(ddesc, batch, plan.max_m, eng, plan.lds_serial, s);
     else if (is_phased(opts))
       e = launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n, plan.max_m,
-                                  plan.lds1, plan.lds2, plan.lds3, s);
+                                  plan.lds1, plan.lds2, plan.lds3, eng, s);
     else
-      e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync, plan.max_n,
-                            plan.max_m, plan.lds_persist, nullptr, s);
+      e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync, plan.max_m, eng,
+                            plan.lds_persist, nullptr, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;

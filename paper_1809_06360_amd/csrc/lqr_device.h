@@ -72,12 +72,12 @@ LQR_DEV void load_stage(const InstDesc& d, int t, const SweepLds& s) {
 }
 
 // Y[:, 0:WX] = P [B | A | c] + [0 | 0 | p]
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void stage_products(const InstDesc& d, const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX, W = s.W;
   double* Y = s.Y;
   const double* p = s.p;
-  pgemm_sub<MF, false, false, false, false>(n, WX, n, s.P, n, s.X, WX, 0, s.P, n, s.X, WX,
+  pgemm_sub<E, false, false, false, false>(n, WX, n, s.P, n, s.X, WX, 0, s.P, n, s.X, WX,
                                         [=](int i, int j, double v) {
                                           if (j == m + n) v += p[i];
                                           Y[i * W + j] = v;
@@ -85,7 +85,7 @@ LQR_DEV void stage_products(const InstDesc& d, const SweepLds& s) {
 }
 
 // G[:, 0:ncols] = B' Y[:, 0:ncols] + [R_t | S_t | r_t | 0]
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncols) {
   const int n = d.n, m = d.m, W = s.W;
   const double* Rt = d.R + (size_t)t * m * m;
@@ -93,7 +93,7 @@ LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncol
   const double* rt = d.r + (size_t)t * m;
   double* G = s.G;
   const int mp = s.mp;
-  pgemm_sub<MF, true, false, false, false>(m, ncols, n, s.X, s.WX, s.Y, W, 0, s.X, s.WX, s.Y, W,
+  pgemm_sub<E, true, false, false, false>(m, ncols, n, s.X, s.WX, s.Y, W, 0, s.X, s.WX, s.Y, W,
                                        [=](int i, int j, double v) {
                                          if (j < m) {
                                            v += Rt[i * m + j];
@@ -108,14 +108,14 @@ LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncol
 
 // [P | p] <- [Q_t | q_t] + A'[PA | Pc+p] - Z'[Z | z], lower triangle computed
 // and mirrored; optionally also written to the global outputs Pg, pg.
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg, double* pg) {
   const int n = d.n, m = d.m, W = s.W;
   const double* Qt = d.Q + (size_t)t * n * n;
   const double* qt = d.q + (size_t)t * n;
   double* P = s.P;
   double* p = s.p;
-  pgemm_sub<MF, true, false, false, true>(n, n + 1, n, s.X + m, s.WX, s.Y + m, W, m, s.G + m * s.mp, s.mp, s.G + m * s.mp, s.mp,
+  pgemm_sub<E, true, false, false, true>(n, n + 1, n, s.X + m, s.WX, s.Y + m, W, m, s.G + m * s.mp, s.mp, s.G + m * s.mp, s.mp,
       [=](int i, int j, double v) {
         if (j < n) {
           if (i >= j) {
@@ -144,7 +144,7 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
 // Writes K_t, k_t and, when requested, chol_t, P_t, p_t for t in [t0, t1).
 // Leaves the value at t0 in LDS (s.P, s.p). Returns (largest failing stage)
 // + 1, or 0; uniform across the workgroup.
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, const double* pend,
                         const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX;
@@ -155,22 +155,22 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
     __syncthreads();
-    stage_products<MM, MF>(d, s);
+    stage_products<MM, E>(d, s);
     __syncthreads();
-    stage_hessian<MM, MF>(d, t, s, WX);
+    stage_hessian<MM, E>(d, t, s, WX);
     __syncthreads();
     // L D L' of H_uu with the right-hand sides [H_ux | h_u | I]: Z = L^{-1}[H_ux | h_u]
     // into G, L^{-1} into G's first m columns (column q of L^{-1} in column q)
     ldl_columns<MM>(s.G, s.mp, m, n + 1, true, s.G, s.mp,
                     d.chol ? d.chol + (size_t)t * m * m : nullptr, s.E, s.bad);
     if (!fail && *s.bad) fail = t + 1;
-    stage_value<MM, MF>(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
+    stage_value<MM, E>(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
                 d.p ? d.p + (size_t)t * n : nullptr);
     {  // [K | k] = -H^{-1}[H_ux | h_u] = -(L^{-1})' Z
       double* Kt = d.K + (size_t)t * m * n;
       double* kt = d.k + (size_t)t * m;
       const int mp = s.mp;
-      pgemm_sub<MF, false, false, false, true>(m, n + 1, 0, s.G, mp, s.G, mp, m, s.G, mp, s.G + m * mp, mp,
+      pgemm_sub<fp64_engine(E), false, false, false, true>(m, n + 1, 0, s.G, mp, s.G, mp, m, s.G, mp, s.G + m * mp, mp,
           [=](int i, int j, double v) {
             if (j < n)
               Kt[i * n + j] = v;
@@ -192,7 +192,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
 //   Psi += Z_W'Z_W,  psi += Gam'c - Z_W'z_h,  Gam <- A'Gam - Z_ux'Z_W
 // (Gam' is the closed-loop transition of the segment). Writes
 // P0 | Gam | Psi | pbar | psi to `out`. Returns as plain_sweep.
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const SweepLds& s) {
   const int n = d.n, m = d.m, W = s.W, WX = s.WX;
   double* Gam = s.Y + WX;  // columns [WX, WX+n) of Y
@@ -208,7 +208,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
     __syncthreads();
-    stage_products<MM, MF>(d, s);
+    stage_products<MM, E>(d, s);
     {  // gc = Gam' c_t (Gam of stage t+1)
       const double* X = s.X;
       for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -218,17 +218,17 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
       }
     }
     __syncthreads();
-    stage_hessian<MM, MF>(d, t, s, W);
+    stage_hessian<MM, E>(d, t, s, W);
     __syncthreads();
     ldl_columns<MM>(s.G, s.mp, m, 2 * n + 1, false, nullptr, 0, nullptr, s.E, s.bad);
     if (!fail && *s.bad) fail = t + 1;
-    stage_value<MM, MF>(d, t, s, nullptr, nullptr);
+    stage_value<MM, E>(d, t, s, nullptr, nullptr);
     {  // [psi-part | Psi-part] = Z_W' [z_h | Z_W]
       double* Psi = s.Psi;
       double* psi = s.psi;
       const double* gc = s.gc;
       const int mp = s.mp;
-      pgemm_sub<MF, false, true, false, false>(n, n + 1, m, s.G + WX * mp, mp, s.G + (m + n) * mp, mp, 0, s.G, mp, s.G, mp,
+      pgemm_sub<E, false, true, false, false>(n, n + 1, m, s.G + WX * mp, mp, s.G + (m + n) * mp, mp, 0, s.G, mp, s.G, mp,
           [=](int i, int j, double v) {
             if (j == 0) {
               psi[i] += gc[i] - v;
@@ -245,7 +245,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
     {  // Gam_new = A'Gam - Z_ux'Z_W  -> the (now free) P A region of Y
       double* Ynew = s.Y + m;
       const int mp = s.mp;
-      pgemm_sub<MF, true, false, false, true>(n, n, n, s.X + m, WX, Gam, W, m, s.G + m * mp, mp, s.G + WX * mp, mp,
+      pgemm_sub<E, true, false, false, true>(n, n, n, s.X + m, WX, Gam, W, m, s.G + m * mp, mp, s.G + WX * mp, mp,
           [=](int i, int j, double v) { Ynew[i * W + j] = v; });
     }
     __syncthreads();
@@ -320,18 +320,18 @@ LQR_DEV void write_terminal(const InstDesc& d) {
     for (int i = threadIdx.x; i < n; i += kThreads) d.p[(size_t)T * n + i] = d.q[(size_t)T * n + i];
 }
 
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
   const int n = d.n, m = d.m, T = d.T, J = d.J;
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   int fail;
   if (seg < J - 1) {
     SweepLds s = carve_sweep(smem, n, m, true, MM);
-    fail = dual_sweep<MM, MF>(d, t0, t1, ws_seg(d.ws, n, seg), s);
+    fail = dual_sweep<MM, E>(d, t0, t1, ws_seg(d.ws, n, seg), s);
   } else {
     SweepLds s = carve_sweep(smem, n, m, false, MM);
     write_terminal(d);
-    fail = plain_sweep<MM, MF>(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
+    fail = plain_sweep<MM, E>(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
     double* b = ws_bnd(d.ws, n, J, J - 1);
     store_block(b, n, s.P, n, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = s.p[i];
@@ -345,7 +345,7 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
 // which is the elimination of x_{t_{j+1}} and the link multiplier
 // mu_j = (I + Pn Psi_j)^{-1}(Pn (Gam_j' x + psi_j) + pn) from the segment's
 // value; forward, x_{t_{j+1}} = F x_{t_j} + f.
-template <int MN, bool MF>
+template <int MN, int E>
 LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   const int n = d.n, J = d.J;
   const int mp = MN + 1, MX = MN;
@@ -386,7 +386,7 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
       sN[(n + r) * mp + i] = Gam[e];
     }
     __syncthreads();
-    pgemm_sub<MF, false, false, false, false>(n, n, n, sA1, n, sPn, n, 0, sA1, n, sPn, n,
+    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, n, sPn, n, 0, sA1, n, sPn, n,
                                           [=](int i, int jj, double v) {
                                             sN[jj * mp + i] = v + (i == jj ? 1.0 : 0.0);
                                           });
@@ -407,11 +407,11 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
       }
     }
     // T1 = Pn F -> sN columns [0, n) ;  v = pn + Pn f
-    pgemm_sub<MF, false, true, false, false>(n, n, n, sPn, n, sN + n * mp, mp, 0, sPn, n, sN, mp,
+    pgemm_sub<fp64_engine(E), false, true, false, false>(n, n, n, sPn, n, sN + n * mp, mp, 0, sPn, n, sN, mp,
                                          [=](int i, int jj, double v) { sN[jj * mp + i] = v; });
     gemv2(n, n, sPn, n, sN + 2 * n * mp, 0, spn, 0, spn, [=](int i, double v) { sv[i] = spn[i] + v; });
     __syncthreads();
-    pgemm_sub<MF, false, true, false, false>(n, n, n, sA1, n, sN, mp, 0, sA1, n, sN, mp,
+    pgemm_sub<fp64_engine(E), false, true, false, false>(n, n, n, sA1, n, sN, mp, 0, sA1, n, sN, mp,
         [=](int i, int jj, double v) {
           if (i >= jj) {
             v += 0.5 * (P0[i * n + jj] + P0[jj * n + i]);
@@ -447,25 +447,25 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   if (threadIdx.x == 0) *d.info = flag[0] ? flag[0] : flag[1];
 }
 
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void phase3_item(const InstDesc& d, int seg, double* smem) {
   const int n = d.n, m = d.m, T = d.T, J = d.J;
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   if (seg < J - 1) {
     SweepLds s = carve_sweep(smem, n, m, false, MM);
     const double* b = ws_bnd(d.ws, n, J, seg + 1);
-    const int fail = plain_sweep<MM, MF>(d, t0, t1, b, b + n * n, s);
+    const int fail = plain_sweep<MM, E>(d, t0, t1, b, b + n * n, s);
     if (fail && threadIdx.x == 0) atomicMax(d.info, fail);
   }
   rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
 }
 
-template <int MM, bool MF>
+template <int MM, int E>
 LQR_DEV void serial_item(const InstDesc& d, double* smem) {
   const int n = d.n, m = d.m, T = d.T;
   SweepLds s = carve_sweep(smem, n, m, false, MM);
   write_terminal(d);
-  const int fail = plain_sweep<MM, MF>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
+  const int fail = plain_sweep<MM, E>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
   rollout(d, 0, T, d.x0, true, smem);
   if (threadIdx.x == 0) *d.info = fail;
 }

@@ -8,21 +8,23 @@
 
 namespace lqr {
 
+// `eng` is the product engine of the sweeps (launch_engine); the linking
+// solve always runs an FP64 engine.
 // Single instance, J = d.J segments: phase 1 (J workgroups), phase 2 (one),
 // phase 3 (J workgroups); ldsN = dynamic LDS bytes of each launch.
-hipError_t launch_parallel(const InstDesc& d, size_t lds1, size_t lds2, size_t lds3,
+hipError_t launch_parallel(const InstDesc& d, size_t lds1, size_t lds2, size_t lds3, int eng,
                            hipStream_t stream);
 // One of the three launches above (phase 1, 2 or 3).
-hipError_t launch_phase(const InstDesc& d, int phase, size_t lds, hipStream_t stream);
+hipError_t launch_phase(const InstDesc& d, int phase, size_t lds, int eng, hipStream_t stream);
 // Single instance, one plain recursion over the whole horizon.
-hipError_t launch_serial(const InstDesc& d, size_t lds, hipStream_t stream);
+hipError_t launch_serial(const InstDesc& d, size_t lds, int eng, hipStream_t stream);
 // Batched forms: descriptors and work items live in device memory.
 // max_n, max_m: largest state and input dimensions in the batch (they select
 // the kernel variant; smaller instances run padded).
 hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items, int nitems,
                                    int ninst, int max_n, int max_m, size_t lds1, size_t lds2,
-                                   size_t lds3, hipStream_t stream);
-hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_n, int max_m, size_t lds,
+                                   size_t lds3, int eng, hipStream_t stream);
+hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, int eng, size_t lds,
                                  hipStream_t stream);
 
 }  // namespace lqr

@@ -12,36 +12,54 @@ namespace lqr {
 // so launches under stream capture normally make none).
 hipError_t ensure_dynamic_lds(const void* kernel, size_t lds);
 
-// Call f with the kernel instantiation K<pad_rows(width), mf>.
-template <template <int, bool> class K, typename F>
-hipError_t with_variant(int width, bool mf, F f) {
+// Call f with the kernel instantiation K<pad_rows(width), eng> (eng: product
+// engine 0, 1 or 2, see pgemm_sub).
+template <template <int, int> class K, typename F>
+hipError_t with_variant(int width, int eng, F f) {
   switch (pad_rows(width)) {
 #define LQR_CASE(W) \
   case W:           \
-    return mf ? f(K<W, true>::fn()) : f(K<W, false>::fn());
+    return eng == 2 ? f(K<W, 2>::fn()) : eng == 1 ? f(K<W, 1>::fn()) : f(K<W, 0>::fn());
     LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
 #undef LQR_CASE
   }
   return hipErrorInvalidValue;
 }
 
+// As with_variant, for kernels that only run FP64 engines (0 or 1).
+template <template <int, int> class K, typename F>
+hipError_t with_variant_fp64(int width, int eng, F f) {
+  switch (pad_rows(width)) {
+#define LQR_CASE(W) \
+  case W:           \
+    return eng == 1 ? f(K<W, 1>::fn()) : f(K<W, 0>::fn());
+    LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
+#undef LQR_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// Product engine of a launch: FP32 matrix cores in the mixed-precision mode,
+// else FP64 matrix cores for n >= kMfmaMinN and the vector ALUs below.
+inline int launch_engine(int max_n, bool mixed) { return mixed ? 2 : max_n >= kMfmaMinN ? 1 : 0; }
+
 // One launcher per kernel. `single` is used when descs == nullptr; otherwise
 // workgroup b runs items[b] (phases 1, 3) or descs[b] (phase 2, serial).
 hipError_t launch_k_phase1(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
-                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+                           unsigned grid, int width, int eng, size_t lds, hipStream_t stream);
 hipError_t launch_k_phase2(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
-                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+                           unsigned grid, int width, int eng, size_t lds, hipStream_t stream);
 hipError_t launch_k_phase3(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
-                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+                           unsigned grid, int width, int eng, size_t lds, hipStream_t stream);
 hipError_t launch_k_serial(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
-                           unsigned grid, int width, bool mf, size_t lds, hipStream_t stream);
+                           unsigned grid, int width, int eng, size_t lds, hipStream_t stream);
 
 // Persistent batched solve: clears the `sync` words, then launches one
 // workgroup per resident slot (occupancy x compute units, at most ntasks),
 // each draining the task queue. lds_items: LDS bytes the tasks need.
 // *grid_out (if not null) receives the grid size.
 hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int ntasks, int ninst,
-                             int32_t* sync, int max_n, int max_m, size_t lds_items,
+                             int32_t* sync, int max_m, int eng, size_t lds_items,
                              int* grid_out, hipStream_t stream);
 
 // Adjoint solve (one workgroup per instance) followed by the gradient

@@ -464,14 +464,84 @@ LQR_DEV void mgemm(int M, int N, int K, const double* A, int lda, const double* 
   mgemm_sub<TA, TB, false, false>(M, N, K, A, lda, B, ldb, 0, A, lda, B, ldb, epi, skip);
 }
 
-// Product on matrix cores (MF, used when the problem has n >= 32 states) or on
-// the vector ALUs with 4x4 register tiles.
-template <bool MF, bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
+// ---------------------------------------------------------------------------
+// FP32 matrix-core product for the mixed-precision mode
+// (v_mfma_f32_16x16x4f32): operands are read from their FP64 storage and
+// rounded to float, products accumulate in float, and epi receives the float
+// sum widened to double. Operand layout as for the FP64 instruction; result
+// register r of lane l is D(i = 4 (l/16) + r, j = l%16).
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((vector_size(16)));
+
+template <bool TA, bool TB, int KC>
+LQR_DEV void mfma32_chunk(f32x4& acc, const double* A, int lda, const double* B, int ldb, int M, int N,
+                          int K, int i, int j, int k0, int lk, float sgn) {
+  float a[KC], b[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) {
+    const int k = k0 + 4 * s + lk;
+    const bool kin = k < K;
+    const int kk = kin ? k : K - 1;
+    a[s] = (kin && i < M) ? sgn * (float)el<TA>(A, lda, i < M ? i : M - 1, kk) : 0.0f;
+    b[s] = (kin && j < N) ? (float)el<TB>(B, ldb, kk, j < N ? j : N - 1) : 0.0f;
+  }
+#pragma unroll
+  for (int s = 0; s < KC; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+}
+
+template <bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
+LQR_DEV void m32gemm_sub(int M, int N,
+                         int K1, const double* A1, int lda1, const double* B1, int ldb1,
+                         int K2, const double* A2, int lda2, const double* B2, int ldb2,
+                         Epi epi, Skip skip = Skip()) {
+  constexpr int KC = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tn = (N + 15) >> 4;
+  const int tiles = ((M + 15) >> 4) * tn;
+  for (int t0 = wave; t0 < tiles; t0 += 2 * kWaves) {
+    const int t1 = t0 + kWaves;
+    const bool has1 = t1 < tiles;
+    const int i0a = (t0 / tn) << 4, j0a = (t0 % tn) << 4;
+    const int i0b = has1 ? (t1 / tn) << 4 : i0a, j0b = has1 ? (t1 % tn) << 4 : j0a;
+    const bool runa = !skip(i0a, j0a, 16, 16), runb = has1 && !skip(i0b, j0b, 16, 16);
+    if (!runa && !runb) continue;
+    f32x4 acca = {0.0f, 0.0f, 0.0f, 0.0f}, accb = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int ia = i0a + li, ja = j0a + li, ib = i0b + li, jb = j0b + li;
+    for (int k0 = 0; k0 < K1; k0 += 4 * KC) {
+      mfma32_chunk<TA1, TB1, KC>(acca, A1, lda1, B1, ldb1, M, N, K1, ia, ja, k0, lk, 1.0f);
+      if (has1) mfma32_chunk<TA1, TB1, KC>(accb, A1, lda1, B1, ldb1, M, N, K1, ib, jb, k0, lk, 1.0f);
+    }
+    for (int k0 = 0; k0 < K2; k0 += 4 * KC) {
+      mfma32_chunk<TA2, TB2, KC>(acca, A2, lda2, B2, ldb2, M, N, K2, ia, ja, k0, lk, -1.0f);
+      if (has1) mfma32_chunk<TA2, TB2, KC>(accb, A2, lda2, B2, ldb2, M, N, K2, ib, jb, k0, lk, -1.0f);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lk + r;
+      if (runa && i0a + i < M && j0a + li < N) epi(i0a + i, j0a + li, (double)acca[r]);
+      if (runb && i0b + i < M && j0b + li < N) epi(i0b + i, j0b + li, (double)accb[r]);
+    }
+  }
+}
+
+// Product engines. E = 0: FP64 on the vector ALUs with 4x4 register tiles
+// (problems with fewer than 32 states); E = 1: FP64 matrix cores; E = 2: FP32
+// matrix cores with FP32 accumulation (mixed-precision mode).
+constexpr int kEngValu = 0, kEngMfma64 = 1, kEngMfma32 = 2;
+
+// The FP64 engine that stands in for E where the product must stay in FP64
+// (Cholesky solves, gains, the linking solve).
+LQR_HD constexpr int fp64_engine(int E) { return E == kEngMfma32 ? kEngMfma64 : E; }
+
+template <int E, bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
 LQR_DEV void pgemm_sub(int M, int N,
                        int K1, const double* A1, int lda1, const double* B1, int ldb1,
                        int K2, const double* A2, int lda2, const double* B2, int ldb2,
                        Epi epi, Skip skip = Skip()) {
-  if constexpr (MF)
+  if constexpr (E == kEngMfma32)
+    m32gemm_sub<TA1, TB1, TA2, TB2>(M, N, K1, A1, lda1, B1, ldb1, K2, A2, lda2, B2, ldb2, epi, skip);
+  else if constexpr (E == kEngMfma64)
     mgemm_sub<TA1, TB1, TA2, TB2>(M, N, K1, A1, lda1, B1, ldb1, K2, A2, lda2, B2, ldb2, epi, skip);
   else
     gemm_sub<4, 4, TA1, TB1, TA2, TB2>(M, N, K1, A1, lda1, B1, ldb1, K2, A2, lda2, B2, ldb2, epi, skip);

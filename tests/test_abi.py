@@ -178,3 +178,20 @@ def test_planner_splits_long_single_instances_more_than_short_ones():
     # a batch that fills the device on its own needs no splitting
     segs, _ = L.plan_segments([(16, 8, 128)] * 512)
     assert set(segs) == {1}
+
+
+def test_precision_modes():
+    """FP64 and mixed precision plan the same workspace; FP32 is rejected; the
+    mixed-precision workload (n = 128) does not fit the LDS-resident kernels."""
+    a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("fp64"))
+    b = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("mixed"))
+    assert a == b
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(ctypes.byref(_prob(16, 8, 128, 0)), 1, L.options("fp32"))
+    assert e.value.status == L.ERR_UNSUPPORTED
+    from synthetic import WORKLOADS
+    (n, m, T), = WORKLOADS["mixed"].dims
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, WORKLOADS["mixed"].segments)), 1,
+                             L.options("mixed"))
+    assert e.value.status == L.ERR_UNSUPPORTED

@@ -1,0 +1,249 @@
+// Phase 2 in logarithmic depth: the linking solve as a suffix scan of the
+// segment summaries under their associative composition.
+//
+// A segment summary S = (P0, Gam, Psi, pbar, psi) describes the segment's
+// cost-to-go as a function of its start state x and of a linear price mu on its
+// end state (the dual form of the endpoint-constrained subproblem of Sec. II-A):
+//   V(x; mu) = 1/2 x'P0 x + (Gam mu + pbar)'x + psi'mu - 1/2 mu'Psi mu,
+// with end state dV/dmu = Gam'x + psi - Psi mu. Joining segment a to the
+// segment b that follows it (minimising over the shared boundary state) gives
+// a summary of the same form; with M = I + P0_b Psi_a and
+//   [X1 | x2 | X3] = M^{-1} [P0_b Gam_a' | P0_b psi_a + pbar_b | Gam_b]:
+//   P0_ab = P0_a + Gam_a X1,          pbar_ab = pbar_a + Gam_a x2,
+//   Gam_ab = Gam_a X3,                Psi_ab = Psi_b + X3' Psi_a Gam_b,
+//   psi_ab = psi_b + X3'(psi_a - Psi_a pbar_b)
+// (M' = I + Psi_a P0_b, so X3' = Gam_b' M'^{-1}). The last segment carries
+// the terminal cost and no price: its summary is its exact value
+// (P0, pbar) = (P, p) at its start with Gam = Psi = psi = 0, and a join
+// with such an "exact" b is exact again. The suffix products
+// S_j (x) S_{j+1} (x) ... (x) S_{J-1} are therefore the exact value functions at
+// the segment boundaries: the quantities the link equation of Sec. II-A
+// eliminates one boundary at a time, here found in ceil(log2 J) rounds of
+// J - dist independent joins (a Kogge-Stone scan, one workgroup per element).
+// The link maps x_{t_{j+1}} = F_j x_{t_j} + f_j then follow in parallel, and a
+// last kernel runs the short forward chain of boundary states.
+#include "lqr_device.h"
+#include "lqr_launch.h"
+
+namespace lqr {
+
+namespace {
+
+LQR_DEV double* scan_elem(double* buf, int n, int j) { return buf + (size_t)j * seg_stride(n); }
+
+}  // namespace
+
+// Scan buffer 0: elements j < J-1 are the phase-1 summaries, element J-1 the
+// last segment's exact value; the instance's linking flag is cleared.
+__global__ __launch_bounds__(kThreads) void k_link_init(InstDesc d) {
+  const int n = d.n, J = d.J, j = blockIdx.x;
+  double* dst = scan_elem(ws_scan(d.ws, n, J, 0), n, j);
+  if (j < J - 1) {
+    const double* src = ws_seg(d.ws, n, j);
+    for (size_t e = threadIdx.x; e < seg_stride(n); e += kThreads) dst[e] = src[e];
+  } else {
+    const double* b = ws_bnd(d.ws, n, J, J - 1);
+    for (int e = threadIdx.x; e < n * n; e += kThreads) dst[e] = b[e];
+    for (int i = threadIdx.x; i < n; i += kThreads) dst[3 * n * n + i] = b[n * n + i];
+  }
+  if (j == 0 && threadIdx.x == 0) d.fail[J] = 0;
+}
+
+// One scan round: out[j] = in[j] (x) in[j + dist], or in[j] when j + dist >= J
+// (then in[j] already reaches the last segment and only its P0, pbar are used).
+template <int MN, int E>
+__global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist, const double* in,
+                                                           double* out) {
+  extern __shared__ double smem[];
+  const int n = d.n, J = d.J, j = blockIdx.x;
+  const int nn = n * n;
+  const double* a = scan_elem(const_cast<double*>(in), n, j);
+  double* o = scan_elem(out, n, j);
+  if (j + dist >= J) {
+    for (int e = threadIdx.x; e < nn; e += kThreads) o[e] = a[e];
+    for (int i = threadIdx.x; i < n; i += kThreads) o[3 * nn + i] = a[3 * nn + i];
+    return;
+  }
+  const double* b = scan_elem(const_cast<double*>(in), n, j + dist);
+  const bool exact_b = j + 2 * dist - 1 >= J - 1;
+  const double *P0a = a, *Ga = a + nn, *Psa = a + 2 * nn, *pa = a + 3 * nn, *psa = pa + n;
+  const double *P0b = b, *Gb = b + nn, *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
+  const int mp = MN + 1;
+  const int nc = exact_b ? 2 * n + 1 : 3 * n + 1;
+  double* sN = smem;                     // mp x nc column-major: [M | RHS] -> [. | X1 | x2 | X3]
+  double* sW = sN + mp * (3 * n + 1);    // n x n row-major: Psi_a Gam_b
+  double* sv = sW + nn;                  // psi_a - Psi_a pbar_b
+  double* gjb = sv + n;
+  int* prow = reinterpret_cast<int*>(gjb + 3 * MN + 2);
+  int* flag = prow + MN;
+  if (threadIdx.x == 0) flag[0] = 0;
+  constexpr int E64 = fp64_engine(E);
+  pgemm_sub<E64, false, false, false, false>(n, n, n, P0b, n, Psa, n, 0, P0b, n, Psa, n,
+      [=](int i, int c, double v) { sN[c * mp + i] = v + (i == c ? 1.0 : 0.0); });
+  pgemm_sub<E64, false, true, false, false>(n, n, n, P0b, n, Ga, n, 0, P0b, n, Ga, n,
+      [=](int i, int c, double v) { sN[(n + c) * mp + i] = v; });
+  gemv2(n, n, P0b, n, psa, 0, psa, 0, psa, [=](int i, double v) { sN[2 * n * mp + i] = pb[i] + v; });
+  if (!exact_b)
+    for (int e = threadIdx.x; e < nn; e += kThreads) {
+      const int r = e / n, c = e - r * n;
+      sN[(2 * n + 1 + c) * mp + r] = Gb[e];
+    }
+  __syncthreads();
+  gj_columns<MN>(sN, mp, n, nc, gjb, prow, flag);
+  double* oP0 = o;
+  double* oG = o + nn;
+  double* oPs = o + 2 * nn;
+  double* op = o + 3 * nn;
+  double* ops = op + n;
+  pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, n, sN + n * mp, mp, 0, Ga, n, sN, mp,
+      [=](int i, int c, double v) {
+        if (i >= c) {
+          v += 0.5 * (P0a[i * n + c] + P0a[c * n + i]);
+          oP0[i * n + c] = v;
+          oP0[c * n + i] = v;
+        }
+      },
+      SkipUpper{n});
+  gemv2(n, n, Ga, n, sN + 2 * n * mp, 0, sv, 0, sv, [=](int i, double v) { op[i] = pa[i] + v; });
+  if (!exact_b) {
+    pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, n, sN + (2 * n + 1) * mp, mp, 0, Ga, n, sN, mp,
+        [=](int i, int c, double v) { oG[i * n + c] = v; });
+    pgemm_sub<E64, false, false, false, false>(n, n, n, Psa, n, Gb, n, 0, Psa, n, Gb, n,
+        [=](int i, int c, double v) { sW[i * n + c] = v; });
+    gemv2(n, n, Psa, n, pb, 0, pb, 0, pb, [=](int i, double v) { sv[i] = psa[i] - v; });
+    __syncthreads();
+    pgemm_sub<E64, false, false, false, false>(n, n, n, sN + (2 * n + 1) * mp, mp, sW, n, 0, sW, n, sW, n,
+        [=](int i, int c, double v) {
+          if (i >= c) {
+            v += 0.5 * (Psb[i * n + c] + Psb[c * n + i]);
+            oPs[i * n + c] = v;
+            oPs[c * n + i] = v;
+          }
+        },
+        SkipUpper{n});
+    gemv2(n, n, sN + (2 * n + 1) * mp, mp, sv, 0, sv, 0, sv,
+          [=](int i, double v) { ops[i] = psb[i] + v; });
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
+}
+
+// Boundary values from the scan result, and the link maps
+//   [F_j | f_j] = N^{-1}[Gam_j' | psi_j - Psi_j p_{t_{j+1}}],  N = I + Psi_j P_{t_{j+1}}
+// (one workgroup per boundary; the last workgroup only copies its value).
+template <int MN, int E>
+__global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double* fin) {
+  extern __shared__ double smem[];
+  const int n = d.n, J = d.J, j = blockIdx.x;
+  const int nn = n * n;
+  {
+    const double* s = scan_elem(const_cast<double*>(fin), n, j);
+    double* bnd = ws_bnd(d.ws, n, J, j);
+    for (int e = threadIdx.x; e < nn; e += kThreads) bnd[e] = s[e];
+    for (int i = threadIdx.x; i < n; i += kThreads) bnd[nn + i] = s[3 * nn + i];
+  }
+  if (j >= J - 1) return;
+  const double* nx = scan_elem(const_cast<double*>(fin), n, j + 1);
+  const double* Pn = nx;
+  const double* pn = nx + 3 * nn;
+  const double* sg = ws_seg(d.ws, n, j);
+  const double *Gam = sg + nn, *Psi = sg + 2 * nn, *psi = sg + 3 * nn + n;
+  const int mp = MN + 1;
+  double* sN = smem;  // mp x (2n+1) column-major: [N | Gam' | w] -> [. | F | f]
+  double* gjb = sN + mp * (2 * n + 1);
+  int* prow = reinterpret_cast<int*>(gjb + 3 * MN + 2);
+  int* flag = prow + MN;
+  if (threadIdx.x == 0) flag[0] = 0;
+  constexpr int E64 = fp64_engine(E);
+  pgemm_sub<E64, false, false, false, false>(n, n, n, Psi, n, Pn, n, 0, Psi, n, Pn, n,
+      [=](int i, int c, double v) { sN[c * mp + i] = v + (i == c ? 1.0 : 0.0); });
+  for (int e = threadIdx.x; e < nn; e += kThreads) {
+    const int r = e / n, i = e - r * n;
+    sN[(n + r) * mp + i] = Gam[e];
+  }
+  gemv2(n, n, Psi, n, pn, 0, pn, 0, pn, [=](int i, double v) { sN[2 * n * mp + i] = psi[i] - v; });
+  __syncthreads();
+  gj_columns<MN>(sN, mp, n, 2 * n + 1, gjb, prow, flag);
+  double* lk = ws_link(d.ws, n, J, j);
+  for (int e = threadIdx.x; e < n * (n + 1); e += kThreads) {
+    const int c = e / n, r = e - c * n;
+    const double v = sN[(n + c) * mp + r];
+    if (c < n)
+      lk[r * n + c] = v;
+    else
+      lk[nn + r] = v;
+  }
+  if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
+}
+
+// Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, and the
+// instance's info word (a stage failure of phase 1 takes precedence).
+__global__ __launch_bounds__(kThreads) void k_link_forward(InstDesc d) {
+  extern __shared__ double smem[];
+  const int n = d.n, J = d.J;
+  double* sx = smem;
+  double* sxn = smem + n;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    sx[i] = d.x0[i];
+    ws_bnd(d.ws, n, J, 0)[n * n + n + i] = d.x0[i];
+  }
+  __syncthreads();
+  for (int j = 0; j < J - 1; ++j) {
+    const double* lk = ws_link(d.ws, n, J, j);
+    gemv2(n, n, lk, n, sx, 0, sx, 0, sx, [=](int i, double v) { sxn[i] = lk[n * n + i] + v; });
+    __syncthreads();
+    double* xb = ws_bnd(d.ws, n, J, j + 1) + n * n + n;
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+      sx[i] = sxn[i];
+      xb[i] = sxn[i];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int f = 0;
+    for (int j = 0; j < J; ++j) f = max(f, d.fail[j]);
+    *d.info = f ? f : d.fail[J];
+  }
+}
+
+template <int W, int M>
+struct k_link_combine_ref {
+  static auto fn() { return &k_link_combine<W, M>; }
+};
+template <int W, int M>
+struct k_link_maps_ref {
+  static auto fn() { return &k_link_maps<W, M>; }
+};
+
+hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
+  const int J = d.J, n = d.n;
+  const int eng = launch_engine(n, false);
+  hipLaunchKernelGGL(k_link_init, dim3(J), dim3(kThreads), 0, stream, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int src = 0;
+  for (int dist = 1; dist < J; dist *= 2) {
+    const double* in = ws_scan(d.ws, n, J, src);
+    double* out = ws_scan(d.ws, n, J, 1 - src);
+    e = with_variant_fp64<k_link_combine_ref>(n, eng, [&](auto k) -> hipError_t {
+      hipError_t e2 = ensure_dynamic_lds((const void*)k, lds);
+      if (e2 != hipSuccess) return e2;
+      hipLaunchKernelGGL(k, dim3(J), dim3(kThreads), lds, stream, d, dist, in, out);
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    src = 1 - src;
+  }
+  const double* fin = ws_scan(d.ws, n, J, src);
+  e = with_variant_fp64<k_link_maps_ref>(n, eng, [&](auto k) -> hipError_t {
+    hipError_t e2 = ensure_dynamic_lds((const void*)k, lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(k, dim3(J), dim3(kThreads), lds, stream, d, fin);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_link_forward, dim3(1), dim3(kThreads), 2 * n * sizeof(double) + 64, stream, d);
+  return hipGetLastError();
+}
+
+}  // namespace lqr

@@ -155,6 +155,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     plan->lds_serial = std::max(plan->lds_serial, std::max(plain, rollout_lds(p.n, p.m)));
     plan->lds1 = std::max(plan->lds1, Ji > 1 ? sweep_lds(p.n, p.m, true, mw) : plain);
     plan->lds2 = std::max(plan->lds2, couple_lds(p.n, pad_rows(plan->max_n)));
+    if (batch == 1 && use_link_tree(p.n, Ji))
+      plan->lds2 = std::max(plan->lds2, link_tree_lds(p.n, pad_rows(p.n)));
     plan->lds3 = std::max(plan->lds3, std::max(plain, rollout_lds(p.n, p.m)));
     if (!serial) plan->lds_persist = std::max(plan->lds_persist, couple_lds(p.n, persist_nw(mf)));
   }
@@ -172,7 +174,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
     const int Ji = J[i];
-    const size_t bytes = align_up(ws_doubles(p.n, Ji) * sizeof(double)) + align_up(sizeof(int32_t) * Ji);
+    const size_t bytes = align_up(ws_doubles(p.n, Ji) * sizeof(double)) +
+                         align_up(sizeof(int32_t) * fail_words(Ji));
     plan->inst[i].ws_off = off;
     plan->inst[i].ws_bytes = bytes;
     off += bytes;

@@ -62,6 +62,11 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
                              int32_t* sync, int max_m, int eng, size_t lds_items,
                              int* grid_out, hipStream_t stream);
 
+// Single-instance linking solve in logarithmic depth (k_link_tree.hip):
+// ceil(log2 J) scan rounds, the link maps, the forward chain of boundary
+// states. lds: link_tree_lds of the instance.
+hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream);
+
 // Adjoint solve (one workgroup per instance) followed by the gradient
 // outer products (one workgroup per (instance, kAdjStages stages) block).
 hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, int nblocks,

@@ -82,9 +82,11 @@ LQR_HD size_t seg_stride(int n) { return 3 * (size_t)n * n + 2 * (size_t)n; }
 LQR_HD size_t bnd_stride(int n) { return (size_t)n * n + 2 * (size_t)n; }
 LQR_HD size_t link_stride(int n) { return (size_t)n * n + (size_t)n; }
 
+//  scan[w][j], w = 0, 1, j < J: two buffers of J summaries (seg layout) for
+//                    the logarithmic-depth linking solve
 LQR_HD size_t ws_doubles(int n, int J) {
   return (size_t)(J - 1) * seg_stride(n) + (size_t)J * bnd_stride(n) +
-         (size_t)(J - 1) * link_stride(n);
+         (size_t)(J - 1) * link_stride(n) + 2 * (size_t)J * seg_stride(n);
 }
 LQR_HD double* ws_seg(double* ws, int n, int j) { return ws + (size_t)j * seg_stride(n); }
 LQR_HD double* ws_bnd(double* ws, int n, int J, int j) {
@@ -94,6 +96,20 @@ LQR_HD double* ws_link(double* ws, int n, int J, int j) {
   return ws + (size_t)(J - 1) * seg_stride(n) + (size_t)J * bnd_stride(n) +
          (size_t)j * link_stride(n);
 }
+
+LQR_HD double* ws_scan(double* ws, int n, int J, int w) {
+  return ws + (size_t)(J - 1) * seg_stride(n) + (size_t)J * bnd_stride(n) +
+         (size_t)(J - 1) * link_stride(n) + (size_t)w * J * seg_stride(n);
+}
+
+// Int32 words per instance after the scratch: J per-segment stage-failure
+// words, then the linking-failure word.
+LQR_HD size_t fail_words(int J) { return (size_t)J + 1; }
+
+// The single-instance linking solve runs in logarithmic depth (scan of the
+// segment summaries) from this many segments on, and serially below.
+constexpr int kTreeMinJ = 8;
+LQR_HD bool use_link_tree(int n, int J) { return J >= kTreeMinJ && n <= 64; }
 
 // LDS footprints in bytes (FP64). The sweep keeps, per workgroup:
 //  sP  n x n           value Hessian of the next stage
@@ -139,6 +155,15 @@ LQR_HD size_t couple_lds(int n, int nw);
 // Register width of the linking solve inside the persistent kernel: one
 // width per product engine (MFMA variants serve n <= 64, VALU ones n < 32).
 LQR_HD constexpr int persist_nw(bool mf) { return mf ? 64 : 32; }
+
+// Join of two summaries: [M | RHS] mp x (3n+1) column-major, Psi_a Gam_b
+// (n x n), a vector, Gauss-Jordan exchange and pivots (the link-map kernel
+// uses less).
+LQR_HD size_t link_tree_lds(int n, int nw) {
+  const size_t mx = (size_t)nw, mp = mx + 1;
+  const size_t dbl = mp * (3 * (size_t)n + 1) + (size_t)n * n + n + 3 * mx + 2;
+  return dbl * 8 + (mx + 4) * 4 + 64;
+}
 
 // Forward simulation: x_t and x_{t+1} (n each), u_t (m).
 LQR_HD size_t rollout_lds(int n, int m) { return (2 * (size_t)n + m) * 8 + 64; }

@@ -177,34 +177,65 @@ __global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double
 }
 
 // Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, and the
-// instance's info word (a stage failure of phase 1 takes precedence).
-__global__ __launch_bounds__(kThreads) void k_link_forward(InstDesc d) {
+// instance's info word (a stage failure of phase 1 takes precedence). The
+// chain is serial and latency-bound, so it runs in one wave: lane i keeps row
+// i of F_j in registers (row i of F_{j+1} is loaded while step j computes)
+// and the state vector is exchanged through LDS with wave-level ordering.
+template <int MN>
+__global__ __launch_bounds__(64) void k_link_forward(InstDesc d) {
   extern __shared__ double smem[];
-  const int n = d.n, J = d.J;
+  const int n = d.n, J = d.J, lane = threadIdx.x;
   double* sx = smem;
-  double* sxn = smem + n;
-  for (int i = threadIdx.x; i < n; i += kThreads) {
-    sx[i] = d.x0[i];
-    ws_bnd(d.ws, n, J, 0)[n * n + n + i] = d.x0[i];
+  const bool row = lane < n;
+  const double xi0 = row ? d.x0[lane] : 0.0;
+  if (row) {
+    sx[lane] = xi0;
+    ws_bnd(d.ws, n, J, 0)[n * n + n + lane] = xi0;
   }
-  __syncthreads();
+  double cur[MN], nxt[MN];
+#pragma unroll
+  for (int k = 0; k < MN; ++k) nxt[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < MN; ++k) cur[k] = 0.0;
+  if (J > 1 && row) {
+    const double* F = ws_link(d.ws, n, J, 0) + lane * n;
+#pragma unroll
+    for (int k = 0; k < MN; ++k) cur[k] = k < n ? F[k] : 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   for (int j = 0; j < J - 1; ++j) {
     const double* lk = ws_link(d.ws, n, J, j);
-    gemv2(n, n, lk, n, sx, 0, sx, 0, sx, [=](int i, double v) { sxn[i] = lk[n * n + i] + v; });
-    __syncthreads();
-    double* xb = ws_bnd(d.ws, n, J, j + 1) + n * n + n;
-    for (int i = threadIdx.x; i < n; i += kThreads) {
-      sx[i] = sxn[i];
-      xb[i] = sxn[i];
+    if (j + 1 < J - 1 && row) {
+      const double* F = ws_link(d.ws, n, J, j + 1) + lane * n;
+#pragma unroll
+      for (int k = 0; k < MN; ++k) nxt[k] = k < n ? F[k] : 0.0;
     }
-    __syncthreads();
+    double acc = row ? lk[n * n + lane] : 0.0;
+#pragma unroll
+    for (int k = 0; k < MN; ++k) acc = fma(cur[k], sx[k < n ? k : 0], acc);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (row) {
+      sx[lane] = acc;
+      ws_bnd(d.ws, n, J, j + 1)[n * n + n + lane] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < MN; ++k) cur[k] = nxt[k];
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     int f = 0;
     for (int j = 0; j < J; ++j) f = max(f, d.fail[j]);
     *d.info = f ? f : d.fail[J];
   }
 }
+
+template <int W, int M>
+struct k_link_forward_ref {
+  static auto fn() { return &k_link_forward<W>; }
+};
 
 template <int W, int M>
 struct k_link_combine_ref {
@@ -242,8 +273,10 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_link_forward, dim3(1), dim3(kThreads), 2 * n * sizeof(double) + 64, stream, d);
-  return hipGetLastError();
+  return with_variant_fp64<k_link_forward_ref>(n, 0, [&](auto k) -> hipError_t {
+    hipLaunchKernelGGL(k, dim3(1), dim3(64), 64 * sizeof(double), stream, d);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace lqr

@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="large", choices=["small", "large", "batched"])
+    ap.add_argument("--workload", default="large", choices=["small", "large", "batched", "diff"])
     ap.add_argument("--no-batched-summary", action="store_true",
                     help="skip the short batched-workload measurement added to the single-instance line")
     ap.add_argument("--serial-steps", type=int, default=5)
@@ -176,6 +176,9 @@ def main():
 
     if args.workload == "batched":
         print(json.dumps(run_batched(args, WORKLOADS["batched"])), flush=True)
+        return
+    if args.workload == "diff":
+        print(json.dumps(run_diff(args, WORKLOADS["diff"])), flush=True)
         return
 
     w = WORKLOADS[args.workload]
@@ -356,15 +359,95 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_batched_summary:
+        bargs = argparse.Namespace(steps=5, warmup=2, serial_steps=2, cpu_seconds=0.0)
         try:
-            bargs = argparse.Namespace(steps=5, warmup=2, serial_steps=2, cpu_seconds=0.0)
             b = run_batched(bargs, WORKLOADS["batched"])
             result["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "config", "phased",
                                                    "serial_gpu", "speedup_vs_serial_gpu", "max_rel_err",
                                                    "roofline")}
         except Exception as exc:  # the headline line must still be printed
             result["batched"] = {"error": repr(exc)}
+        try:
+            dres = run_diff(bargs, WORKLOADS["diff"])
+            result["differentiable"] = {k: dres[k] for k in ("value", "unit", "ms_per_step", "config",
+                                                           "forward_ms", "backward_ms", "roofline")}
+        except Exception as exc:
+            result["differentiable"] = {"error": repr(exc)}
     print(json.dumps(result), flush=True)
+
+
+def run_diff(args, w):
+    """The differentiable workload: forward solve of the whole batch (one
+    persistent launch) and the adjoint (lqr_backward: adjoint solve + gradient
+    outer products) for the loss sum |x|^2 + |u|^2, timed with HIP events on
+    the launch stream; the CPU baseline is the oracle's forward + adjoint on a
+    sample of the instances."""
+    import numpy as np
+    import torch
+
+    import paper_1809_06360_amd as L
+    from synthetic import make_instance
+
+    dev = torch.device("cuda:0")
+    log("differentiable workload %s: %d instances" % (w.name, w.batch))
+    probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
+    datas = [{k: torch.from_numpy(v).to(dev) for k, v in p.items()} for p in probs]
+    keys = ("A", "B", "c", "Q", "q", "R", "r", "x0")
+    outs, ws = L.solve_batched(datas, with_chol=True)
+    gx = [2.0 * o["x"] for o in outs]
+    gu = [2.0 * o["u"] for o in outs]
+    grads = L.backward(datas, outs, gx, gu, which=keys)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for _ in range(args.warmup):
+        L.solve_batched(datas, outputs=outs, workspace=ws)
+        L.backward(datas, outs, gx, gu, which=keys, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(K):
+        ev[s_][0].record(stream)
+        L.solve_batched(datas, outputs=outs, workspace=ws)
+        ev[s_][1].record(stream)
+        L.backward(datas, outs, gx, gu, which=keys, workspace=ws)
+        ev[s_][2].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    bwd = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    n, m, T = w.dims[0]
+    # the adjoint's algorithmic HBM bytes (FP64): read A, B, K, P, chol, x, u,
+    # lam and the upstream gradients; write the adjoint solution scratch and
+    # the gradients of A, B, c, Q, q, R, r, x0
+    rd = T * (n * n + n * m + m * n + m * m) + (T + 1) * n * n + 3 * (T + 1) * n + 2 * T * m
+    wr = (T * (n * n + n * m + n + m * m + m) + (T + 1) * (n * n + n) + n) + 3 * (T + 1) * n + 2 * T * m
+    bbytes = 8.0 * w.batch * (rd + wr)
+    achieved = bbytes / (bwd * 1e-3) / 1e9
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        t = time.perf_counter()
+        done = 0
+        while done < w.batch and time.perf_counter() - t < args.cpu_seconds:
+            sol = oracle.solve(probs[done])
+            oracle.backward(probs[done], sol, 2.0 * sol["x"], 2.0 * sol["u"])
+            done += 1
+        dt = time.perf_counter() - t
+        cpu = {"value": done / dt, "unit": "forward+adjoint solves/s", "cores": 1, "kind": "oracle",
+               "sample": "forward + adjoint of the first %d instances on one host core, %.1f s" % (done, dt)}
+    return {
+        "metric": METRIC, "value": w.batch * 1e3 / ms, "unit": "forward+adjoint solves/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "instances": w.batch, "n": n, "m": m, "T": T,
+                   "loss": "sum |x_t|^2 + |u_t|^2", "gradients": list(keys)},
+        "forward_ms": fwd, "backward_ms": bwd,
+        "roofline": {"kernel": "lqr_backward (k_adjoint_solve + k_adjoint_grad)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": bwd},
+        "cpu_baseline": cpu,
+    }
 
 
 def batch_flops(dims, segs):

@@ -52,7 +52,7 @@ constexpr int kComputeUnits = 256;
 // linking solve must fit the kernels' register and LDS budgets.
 bool can_split(int n, int m, int mw, int nw) {
   return n <= 64 && 2 * n + 1 <= 256 && sweep_fits_regs(n, m, true) &&
-         sweep_lds(n, m, true, mw) <= kLdsGfx950 && couple_lds(n, nw) <= kLdsGfx950;
+         dual_lds(n, m, mw) <= kLdsGfx950 && couple_lds(n, nw) <= kLdsGfx950;
 }
 
 struct InstPlan {
@@ -126,8 +126,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     plan->max_n = std::max(plan->max_n, p.n);
     plan->max_m = std::max(plan->max_m, p.m);
   }
-  const int mw = pad_rows(plan->max_m);
   const int eng = launch_engine(plan->max_n, is_mixed(opts));
+  const int mw = pad_rows(kernel_width(plan->max_m, eng));
   const bool mf = eng != 0;
   // linking-solve width: that of the phased kernel or of the persistent one
   const int nw = std::max(pad_rows(plan->max_n), persist_nw(mf));
@@ -138,7 +138,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     const bool split = !serial && can_split(p.n, p.m, mw, nw);
     if (p.segments > 1 && !split && !serial) return LQR_ERR_UNSUPPORTED;
     tin[i] = TuneInst{p.n, p.m, p.T, serial ? 1 : p.segments, split};
-    lds_guess = std::max(lds_guess, sweep_lds(p.n, p.m, split, mw));
+    lds_guess = std::max(lds_guess, sweep_lds(p.n, p.m, false, mw));
+    if (split) lds_guess = std::max(lds_guess, dual_lds(p.n, p.m, mw));
     if (split) lds_guess = std::max(lds_guess, couple_lds(p.n, nw));
   }
   std::vector<int> J = tune_segments(tin, mw, mf, planned_slots(lds_guess));
@@ -153,7 +154,9 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     const size_t plain = sweep_lds(p.n, p.m, false, mw);
     if (plain > lds_max || !sweep_fits_regs(p.n, p.m, false)) return LQR_ERR_UNSUPPORTED;
     plan->lds_serial = std::max(plan->lds_serial, std::max(plain, rollout_lds(p.n, p.m)));
-    plan->lds1 = std::max(plan->lds1, Ji > 1 ? sweep_lds(p.n, p.m, true, mw) : plain);
+    // phase 1 runs the parametric sweep on segments j < J-1 and the plain
+    // recursion on the last one; the streamed sweep can need less than the latter
+    plan->lds1 = std::max(plan->lds1, Ji > 1 ? std::max(dual_lds(p.n, p.m, mw), plain) : plain);
     plan->lds2 = std::max(plan->lds2, couple_lds(p.n, pad_rows(plan->max_n)));
     if (batch == 1 && use_link_tree(p.n, Ji))
       plan->lds2 = std::max(plan->lds2, link_tree_lds(p.n, pad_rows(p.n)));
@@ -463,7 +466,8 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
       e = launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n, plan.max_m,
                                   plan.lds1, plan.lds2, plan.lds3, eng, s);
     else
-      e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync, plan.max_m, eng,
+      e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync,
+                            kernel_width(plan.max_m, eng), eng,
                             plan.lds_persist, nullptr, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {

@@ -266,6 +266,126 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   return fail;
 }
 
+// Streamed form of dual_sweep for segments whose resident layout exceeds
+// the LDS: Gamma and Psi live in global memory (Psi accumulated in place in
+// `out`, Gamma alternating between `out` and the scratch `gtmp`, n x n) and
+// A_t is read from global memory by the products that use it. LDS holds P, p,
+// [B_t | c_t], P[B_t | A_t | c_t] + [0 | 0 | p] and the Hessian block G.
+// Same recursion and results as dual_sweep; LDS footprint sweep_lds_gs.
+template <int MM, int E>
+LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double* gtmp,
+                          double* smem) {
+  const int n = d.n, m = d.m, nn = n * n;
+  const int WX = m + 1, WY = m + n + 1, mp = MM + 1;
+  double* P = smem;
+  double* p = P + nn;
+  double* X = p + n;             // n x (m+1): [B | c]
+  double* Y = X + n * WX;        // n x (m+n+1): [PB | PA | Pc+p]
+  double* G = Y + n * WY;        // mp x (m+2n+1) column-major
+  double* Eb = G + mp * (m + 2 * n + 1);
+  double* psi = Eb + 3 * MM;
+  double* gc = psi + n;
+  int* bad = reinterpret_cast<int*>(gc + n);
+  double* Psi = out + 2 * nn;
+  double* Gam = out + nn;
+  double* Gn = gtmp;
+  if (threadIdx.x == 0) *bad = 0;
+  fill_block(P, n, n, n, 0.0, 0.0);
+  fill_block(Psi, n, n, n, 0.0, 0.0);
+  fill_block(Gam, n, n, n, 0.0, 1.0);
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    p[i] = 0.0;
+    psi[i] = 0.0;
+  }
+  int fail = 0;
+  for (int t = t1 - 1; t >= t0; --t) {
+    const double* At = d.A + (size_t)t * nn;
+    const double* ct = d.c + (size_t)t * n;
+    const double* Rt = d.R + (size_t)t * m * m;
+    const double* St = d.S ? d.S + (size_t)t * m * n : nullptr;
+    const double* rt = d.r + (size_t)t * m;
+    load_block(X, WX, d.B + (size_t)t * n * m, m, n, m);
+    for (int i = threadIdx.x; i < n; i += kThreads) X[i * WX + m] = ct[i];
+    __syncthreads();
+    // Y = P [B | A | c] + [0 | 0 | p]
+    pgemm_sub<E, false, false, false, false>(n, m + 1, n, P, n, X, WX, 0, P, n, X, WX,
+        [=](int i, int j, double v) {
+          if (j < m) Y[i * WY + j] = v;
+          else Y[i * WY + m + n] = v + p[i];
+        });
+    pgemm_sub<E, false, false, false, false>(n, n, n, P, n, At, n, 0, P, n, At, n,
+        [=](int i, int j, double v) { Y[i * WY + m + j] = v; });
+    for (int i = threadIdx.x; i < n; i += kThreads) {  // gc = Gam' c (Gam of stage t+1)
+      double a = 0.0;
+      for (int k = 0; k < n; ++k) a = fma(Gam[k * n + i], X[k * WX + m], a);
+      gc[i] = a;
+    }
+    __syncthreads();
+    // G = B'[PB | PA | Pc+p | Gam] + [R | S | r | 0]
+    pgemm_sub<E, true, false, false, false>(m, m + n + 1, n, X, WX, Y, WY, 0, X, WX, Y, WY,
+        [=](int i, int j, double v) {
+          if (j < m) v += Rt[i * m + j];
+          else if (j < m + n) { if (St) v += St[i * n + (j - m)]; }
+          else v += rt[i];
+          G[j * mp + i] = v;
+        });
+    pgemm_sub<E, true, false, false, false>(m, n, n, X, WX, Gam, n, 0, X, WX, Gam, n,
+        [=](int i, int j, double v) { G[(m + n + 1 + j) * mp + i] = v; });
+    __syncthreads();
+    ldl_columns<MM>(G, mp, m, 2 * n + 1, false, nullptr, 0, nullptr, Eb, bad);
+    if (!fail && *bad) fail = t + 1;
+    {  // [P | p] <- [Q | q] + A'[PA | Pc+p] - Z_ux'[Z_ux | z_h]
+      const double* Qt = d.Q + (size_t)t * nn;
+      const double* qt = d.q + (size_t)t * n;
+      pgemm_sub<E, true, false, false, true>(n, n + 1, n, At, n, Y + m, WY, m, G + m * mp, mp,
+          G + m * mp, mp,
+          [=](int i, int j, double v) {
+            if (j < n) {
+              if (i >= j) {
+                v += 0.5 * (Qt[i * n + j] + Qt[j * n + i]);
+                P[i * n + j] = v;
+                P[j * n + i] = v;
+              }
+            } else {
+              p[i] = v + qt[i];
+            }
+          },
+          SkipUpper{n});
+    }
+    {  // Psi += Z_W'Z_W (in place, global), psi += Gam'c - Z_W'z_h
+      pgemm_sub<E, false, true, false, false>(n, n + 1, m, G + (m + n + 1) * mp, mp, G + (m + n) * mp, mp,
+          0, G, mp, G, mp,
+          [=](int i, int j, double v) {
+            if (j == 0) {
+              psi[i] += gc[i] - v;
+            } else if (i >= j - 1) {
+              const int jj = j - 1;
+              const double nv = Psi[i * n + jj] + v;
+              Psi[i * n + jj] = nv;
+              Psi[jj * n + i] = nv;
+            }
+          },
+          SkipUpperShift{n, 1});
+    }
+    // Gam <- A'Gam - Z_ux'Z_W into the other buffer
+    pgemm_sub<E, true, false, false, true>(n, n, n, At, n, Gam, n, m, G + m * mp, mp,
+        G + (m + n + 1) * mp, mp, [=](int i, int j, double v) { Gn[i * n + j] = v; });
+    __syncthreads();
+    double* tmp = Gam;
+    Gam = Gn;
+    Gn = tmp;
+  }
+  __syncthreads();
+  store_block(out, n, P, n, n, n);
+  if (Gam != out + nn) store_block(out + nn, n, Gam, n, n, n);
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    out[3 * nn + i] = p[i];
+    out[3 * nn + n + i] = psi[i];
+  }
+  __syncthreads();
+  return fail;
+}
+
 // Forward simulation of stages [t0, t1) from x_{t0} = xs (global):
 // u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t; writes x_t, u_t
 // (and lam_t = P_t x_t + p_t when requested), plus x_T (lam_T) if last.
@@ -326,8 +446,13 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   int fail;
   if (seg < J - 1) {
-    SweepLds s = carve_sweep(smem, n, m, true, MM);
-    fail = dual_sweep<MM, E>(d, t0, t1, ws_seg(d.ws, n, seg), s);
+    if (sweep_lds(n, m, true, MM) <= kLdsSweepMax) {
+      SweepLds s = carve_sweep(smem, n, m, true, MM);
+      fail = dual_sweep<MM, E>(d, t0, t1, ws_seg(d.ws, n, seg), s);
+    } else {
+      double* gtmp = ws_scan(d.ws, n, J, 0) + (size_t)seg * seg_stride(n);
+      fail = dual_sweep_gs<MM, E>(d, t0, t1, ws_seg(d.ws, n, seg), gtmp, smem);
+    }
   } else {
     SweepLds s = carve_sweep(smem, n, m, false, MM);
     write_terminal(d);

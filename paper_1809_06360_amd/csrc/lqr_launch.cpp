@@ -26,11 +26,11 @@ hipError_t ensure_dynamic_lds(const void* kernel, size_t lds) {
 
 hipError_t launch_phase(const InstDesc& d, int phase, size_t lds, int eng, hipStream_t stream) {
   switch (phase) {
-    case 1: return launch_k_phase1(d, nullptr, nullptr, d.J, d.m, eng, lds, stream);
+    case 1: return launch_k_phase1(d, nullptr, nullptr, d.J, kernel_width(d.m, eng), eng, lds, stream);
     case 2:
       if (use_link_tree(d.n, d.J)) return launch_link_tree(d, lds, stream);
       return launch_k_phase2(d, nullptr, nullptr, 1, d.n, launch_engine(d.n, false), lds, stream);
-    case 3: return launch_k_phase3(d, nullptr, nullptr, d.J, d.m, eng, lds, stream);
+    case 3: return launch_k_phase3(d, nullptr, nullptr, d.J, kernel_width(d.m, eng), eng, lds, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -44,7 +44,7 @@ hipError_t launch_parallel(const InstDesc& d, size_t lds1, size_t lds2, size_t l
 }
 
 hipError_t launch_serial(const InstDesc& d, size_t lds, int eng, hipStream_t stream) {
-  return launch_k_serial(d, nullptr, nullptr, 1, d.m, eng, lds, stream);
+  return launch_k_serial(d, nullptr, nullptr, 1, kernel_width(d.m, eng), eng, lds, stream);
 }
 
 hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items, int nitems,
@@ -52,17 +52,19 @@ hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items,
                                    size_t lds3, int eng, hipStream_t stream) {
   const InstDesc none{};
   hipError_t e;
-  if ((e = launch_k_phase1(none, descs, items, nitems, max_m, eng, lds1, stream)) != hipSuccess) return e;
+  if ((e = launch_k_phase1(none, descs, items, nitems, kernel_width(max_m, eng), eng, lds1, stream)) !=
+      hipSuccess)
+    return e;
   if ((e = launch_k_phase2(none, descs, nullptr, ninst, max_n, launch_engine(max_n, false), lds2,
                            stream)) != hipSuccess)
     return e;
-  return launch_k_phase3(none, descs, items, nitems, max_m, eng, lds3, stream);
+  return launch_k_phase3(none, descs, items, nitems, kernel_width(max_m, eng), eng, lds3, stream);
 }
 
 hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, int eng, size_t lds,
                                  hipStream_t stream) {
   const InstDesc none{};
-  return launch_k_serial(none, descs, nullptr, ninst, max_m, eng, lds, stream);
+  return launch_k_serial(none, descs, nullptr, ninst, kernel_width(max_m, eng), eng, lds, stream);
 }
 
 }  // namespace lqr

@@ -43,6 +43,11 @@ hipError_t with_variant_fp64(int width, int eng, F f) {
 // else FP64 matrix cores for n >= kMfmaMinN and the vector ALUs below.
 inline int launch_engine(int max_n, bool mixed) { return mixed ? 2 : max_n >= kMfmaMinN ? 1 : 0; }
 
+// Register width (the m the kernel variant is picked for) of a launch: the
+// matrix-core engines run widths of at least 16 (their width-8 variants are not
+// used), the vector-ALU engine any width.
+inline int kernel_width(int max_m, int eng) { return eng != 0 && max_m < 9 ? 9 : max_m; }
+
 // One launcher per kernel. `single` is used when descs == nullptr; otherwise
 // workgroup b runs items[b] (phases 1, 3) or descs[b] (phase 2, serial).
 hipError_t launch_k_phase1(const InstDesc& single, const InstDesc* descs, const WorkItem* items,

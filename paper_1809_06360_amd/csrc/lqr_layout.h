@@ -145,6 +145,27 @@ LQR_HD size_t sweep_lds(int n, int m, bool dual, int mw) {
   return dbl * 8 + 64;
 }
 
+// LDS a workgroup may hold on gfx950; a segment sweep whose resident layout
+// needs more runs its streamed form (see dual_sweep_gs).
+constexpr size_t kLdsSweepMax = 160 * 1024;
+
+// LDS of the streamed parametric sweep: P, p, [B | c], P[B | A | c] + [0|0|p],
+// the Hessian block (mw+1) x (m+2n+1), exchange vectors, psi and Gam'c
+// (Gamma and Psi stay in global memory).
+LQR_HD size_t sweep_lds_gs(int n, int m, int mw) {
+  const size_t W = (size_t)m + 2 * (size_t)n + 1, mp = (size_t)mw + 1;
+  const size_t dbl = (size_t)n * n + n + (size_t)n * (m + 1) + (size_t)n * (m + n + 1) + mp * W +
+                     3 * (size_t)mw + 2 * (size_t)n;
+  return dbl * 8 + 64;
+}
+
+// LDS the parametric sweep of phase 1 uses: the resident layout if it fits,
+// else the streamed one.
+LQR_HD size_t dual_lds(int n, int m, int mw) {
+  const size_t r = sweep_lds(n, m, true, mw);
+  return r <= kLdsSweepMax ? r : sweep_lds_gs(n, m, mw);
+}
+
 // Problems with at least this many states run their products on matrix cores.
 constexpr int kMfmaMinN = 32;
 

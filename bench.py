@@ -370,7 +370,8 @@ def main():
         try:
             dres = run_diff(bargs, WORKLOADS["diff"])
             result["differentiable"] = {k: dres[k] for k in ("value", "unit", "ms_per_step", "config",
-                                                           "forward_ms", "backward_ms", "roofline")}
+                                                           "forward_ms", "backward_ms", "fp32",
+                                                           "roofline")}
         except Exception as exc:
             result["differentiable"] = {"error": repr(exc)}
     print(json.dumps(result), flush=True)
@@ -416,6 +417,26 @@ def run_diff(args, w):
     ms = (time.perf_counter() - t0) * 1e3 / K
     fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     bwd = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    # the same in the FP32 precision mode (float arrays; float matrix-core
+    # products, double factorizations; adjoint in double on staged arrays)
+    d32 = [{k: v.float() for k, v in d.items()} for d in datas]
+    o32, ws32 = L.solve_batched(d32, precision="fp32", with_chol=True)
+    gx32 = [2.0 * o["x"] for o in o32]
+    gu32 = [2.0 * o["u"] for o in o32]
+    L.backward(d32, o32, gx32, gu32, which=keys)
+    torch.cuda.synchronize()
+    ev32 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for s_ in range(K):
+        ev32[s_][0].record(stream)
+        L.solve_batched(d32, outputs=o32, workspace=ws32, precision="fp32")
+        ev32[s_][1].record(stream)
+        L.backward(d32, o32, gx32, gu32, which=keys, workspace=ws32)
+        ev32[s_][2].record(stream)
+    torch.cuda.synchronize()
+    fwd32 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev32]))
+    bwd32 = float(np.mean([e[1].elapsed_time(e[2]) for e in ev32]))
+    log("fp64 forward %.3f ms backward %.3f ms; fp32 forward %.3f ms backward %.3f ms"
+        % (fwd, bwd, fwd32, bwd32))
     n, m, T = w.dims[0]
     # the adjoint's algorithmic HBM bytes (FP64): read A, B, K, P, chol, x, u,
     # lam and the upstream gradients; write the adjoint solution scratch and
@@ -443,6 +464,10 @@ def run_diff(args, w):
         "config": {"workload": w.name, "instances": w.batch, "n": n, "m": m, "T": T,
                    "loss": "sum |x_t|^2 + |u_t|^2", "gradients": list(keys)},
         "forward_ms": fwd, "backward_ms": bwd,
+        "fp32": {"forward_ms": fwd32, "backward_ms": bwd32,
+                 "solves_per_s": w.batch * 1e3 / (fwd32 + bwd32),
+                 "note": "float inputs/outputs staged as double in the workspace; float "
+                         "matrix-core products, double factorizations; adjoint in double"},
         "roofline": {"kernel": "lqr_backward (k_adjoint_solve + k_adjoint_grad)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": bwd},

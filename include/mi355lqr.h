@@ -71,8 +71,14 @@ typedef enum {
                             assembled and Cholesky-factored in double, the gains and
                             the linking solve are double. lqr_backward computes in
                             double. */
-    LQR_PREC_FP32 = 2    /* everything in float: not supported by this library
-                            version (LQR_ERR_UNSUPPORTED) */
+    LQR_PREC_FP32 = 2    /* float inputs and outputs (every array of lqr_problem_t
+                            and lqr_grad_t). The call converts them to a double
+                            staging area in the workspace, solves as LQR_PREC_MIXED
+                            does (float matrix-core products, double factorizations,
+                            gains and linking solve) and rounds the results back to
+                            float; lqr_backward computes the adjoint in double from the
+                            staged arrays. lqr_solve_phase returns LQR_ERR_UNSUPPORTED
+                            for this precision. */
 } lqr_precision_t;
 
 typedef enum {

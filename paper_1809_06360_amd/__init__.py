@@ -272,7 +272,8 @@ def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "pa
 GRAD_KEYS = ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")
 
 
-def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=None):
+def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=None,
+             precision: str = None):
     """Gradients of a loss l(x, u) with respect to the problem data of a batch
     already solved by ``solve_batched`` (``outs`` must hold K, P, x, u, lam,
     chol). ``dl_dx[i]``, ``dl_du[i]``: upstream gradients of instance i.
@@ -298,7 +299,9 @@ def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=
         g["_keep"] = (gx, gu)
         grads[i] = LqrGrad(gx.data_ptr(), gu.data_ptr(), *[_ptr(g.get(k)) for k in
                                                            ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")])
-    opts = options("fp64", "parallel")
+    if precision is None:
+        precision = "fp32" if datas[0]["A"].dtype == torch.float32 else "fp64"
+    opts = options(precision, "parallel")
     nbytes = lqr_workspace_size(probs, batch, opts)
     device = datas[0]["A"].device
     ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
@@ -344,7 +347,7 @@ def _lqr_function():
                        info=torch.zeros(N, 1, dtype=torch.int32, device=dev))
             datas = _instances(*ts)
             outs = [{k: v[i] for k, v in big.items()} for i in range(N)]
-            solve_batched(datas, outputs=outs)
+            solve_batched(datas, outputs=outs, precision="fp32" if dt == torch.float32 else "fp64")
             ctx.save_for_backward(*ts)
             ctx.big = big
             return big["x"], big["u"]

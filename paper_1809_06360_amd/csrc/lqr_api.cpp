@@ -59,6 +59,7 @@ struct InstPlan {
   int J;
   size_t ws_off;   // bytes from the workspace base
   size_t ws_bytes;
+  size_t stage_off = 0;  // FP32 mode: FP64 staging of the instance's inputs and outputs
 };
 
 // Workspace layout of a call: descriptor table | phase-1/3 work items (phased
@@ -68,7 +69,7 @@ struct BatchPlan {
   std::vector<InstPlan> inst;
   std::vector<TaskItem> tasks;  // persistent launch order (parallel algorithm)
   double est_us = 0.0;          // predicted makespan of the persistent launch
-  size_t items_off = 0, tasks_off = 0, sync_off = 0;
+  size_t items_off = 0, tasks_off = 0, cvt_off = 0, sync_off = 0;
   size_t table_bytes = 0;       // = sync_off
   size_t total_bytes = 0;
   int nitems = 0;
@@ -79,6 +80,10 @@ struct BatchPlan {
 bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL; }
 bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
 bool is_mixed(const lqr_options_t* o) { return o && o->precision == LQR_PREC_MIXED; }
+bool is_f32(const lqr_options_t* o) { return o && o->precision == LQR_PREC_FP32; }
+// FP32 staging conversions per instance in a batched plan's table: up to 9
+// inputs in, 8 outputs out.
+constexpr int kCvtPerInst = 17;
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
@@ -87,7 +92,6 @@ lqr_status_t check_options(const lqr_options_t* o) {
   if (o->precision != LQR_PREC_FP64 && o->precision != LQR_PREC_MIXED &&
       o->precision != LQR_PREC_FP32)
     return LQR_ERR_INVALID_ARG;
-  if (o->precision == LQR_PREC_FP32) return LQR_ERR_UNSUPPORTED;
   return LQR_SUCCESS;
 }
 
@@ -126,7 +130,7 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     plan->max_n = std::max(plan->max_n, p.n);
     plan->max_m = std::max(plan->max_m, p.m);
   }
-  const int eng = launch_engine(plan->max_n, is_mixed(opts));
+  const int eng = launch_engine(plan->max_n, is_mixed(opts) || is_f32(opts));
   const int mw = pad_rows(kernel_width(plan->max_m, eng));
   const bool mf = eng != 0;
   // linking-solve width: that of the phased kernel or of the persistent one
@@ -171,9 +175,18 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
   plan->nitems = items;
   plan->items_off = align_up(sizeof(InstDesc) * (size_t)batch);
   plan->tasks_off = plan->items_off + align_up(sizeof(WorkItem) * (size_t)items);
-  plan->sync_off = plan->tasks_off + align_up(sizeof(TaskItem) * plan->tasks.size());
+  plan->cvt_off = plan->tasks_off + align_up(sizeof(TaskItem) * plan->tasks.size());
+  plan->sync_off = plan->cvt_off +
+                   (is_f32(opts) ? align_up(sizeof(CvtItem) * (size_t)kCvtPerInst * batch) : 0);
   plan->table_bytes = plan->sync_off;
   size_t off = plan->sync_off + align_up(sizeof(int32_t) * sync_words(batch));
+  if (is_f32(opts))
+    for (int i = 0; i < batch; ++i) {
+      const lqr_problem_t& p = probs[i];
+      plan->inst[i].stage_off = off;
+      off += align_up((stage_in_doubles(p.n, p.m, p.T) + stage_out_doubles(p.n, p.m, p.T)) *
+                      sizeof(double));
+    }
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
     const int Ji = J[i];
@@ -234,15 +247,29 @@ lqr_status_t check_device(const BatchPlan& plan) {
 
 // Adjoint layout: AdjDesc table, stage-block table, then per-instance scratch.
 struct AdjPlan {
-  size_t table_bytes = 0, blocks_off = 0, total_bytes = 0;
+  size_t table_bytes = 0, blocks_off = 0, cvt_off = 0, total_bytes = 0;
   int nblocks = 0;
   std::vector<size_t> ws_off;
+  std::vector<size_t> stage_off;  // FP32 mode staging per instance
   size_t lds = 0;
 };
 
-lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap) {
+// FP32 adjoint staging per instance (doubles): A, B, K, P, chol, x, u, lam,
+// dl_dx, dl_du in; dA, dB, dc, dQ, dq, dR, dr, dS, dx0 out.
+size_t adj_stage_doubles(int n, int m, int T) {
+  const size_t t = T, t1 = (size_t)T + 1;
+  const size_t in = t * n * n + t * n * m + t * m * n + t1 * n * n + t * m * m + 2 * t1 * n + t * m +
+                    t1 * n + t * m;
+  const size_t out = t * n * n + t * n * m + t * n + t1 * n * n + t1 * n + t * m * m + t * m +
+                     t * m * n + n;
+  return in + out;
+}
+constexpr int kAdjCvtPerInst = 19;
+
+lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap, bool f32) {
   if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
   ap->ws_off.resize(batch);
+  ap->stage_off.assign(batch, 0);
   int nb = 0;
   for (int i = 0; i < batch; ++i) {
     lqr_status_t st = check_dims(probs[i]);
@@ -253,11 +280,16 @@ lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap) {
   }
   ap->nblocks = nb;
   ap->blocks_off = align_up(sizeof(AdjDesc) * (size_t)batch);
-  ap->table_bytes = ap->blocks_off + align_up(sizeof(int2) * (size_t)nb);
+  ap->cvt_off = ap->blocks_off + align_up(sizeof(int2) * (size_t)nb);
+  ap->table_bytes = ap->cvt_off + (f32 ? align_up(sizeof(CvtItem) * (size_t)kAdjCvtPerInst * batch) : 0);
   size_t off = ap->table_bytes;
   for (int i = 0; i < batch; ++i) {
     ap->ws_off[i] = off;
     off += align_up(adj_ws_doubles(probs[i].n, probs[i].m, probs[i].T) * sizeof(double));
+    if (f32) {
+      ap->stage_off[i] = off;
+      off += align_up(adj_stage_doubles(probs[i].n, probs[i].m, probs[i].T) * sizeof(double));
+    }
   }
   ap->total_bytes = off;
   return LQR_SUCCESS;
@@ -289,6 +321,50 @@ InstDesc make_desc(const lqr_problem_t& p, int J, char* ws_base, size_t ws_off) 
   d.info = p.info;
   d.ws = reinterpret_cast<double*>(ws_base + ws_off);
   d.fail = reinterpret_cast<int32_t*>(ws_base + ws_off + align_up(ws_doubles(p.n, J) * sizeof(double)));
+  return d;
+}
+
+// FP32 mode: the descriptor of an instance whose arrays are the FP64 staging
+// copies at `stage` (inputs A..x0, then outputs K..chol, see stage_in_doubles),
+// and the conversions that fill the inputs and return the requested outputs.
+InstDesc make_desc_f32(const lqr_problem_t& p, int J, char* ws_base, size_t ws_off, size_t stage,
+                       CvtItem* cin, int* nin, CvtItem* cout, int* nout) {
+  InstDesc d = make_desc(p, J, ws_base, ws_off);
+  const int n = p.n, m = p.m, T = p.T;
+  double* q = reinterpret_cast<double*>(ws_base + stage);
+  *nin = 0;
+  *nout = 0;
+  auto in = [&](const void* user, size_t count) -> const double* {
+    double* dst = q;
+    q += count;
+    if (!user) return nullptr;
+    cin[(*nin)++] = CvtItem{user, dst, (int64_t)count, 1, 0};
+    return dst;
+  };
+  d.A = in(p.A, (size_t)T * n * n);
+  d.B = in(p.B, (size_t)T * n * m);
+  d.c = in(p.c, (size_t)T * n);
+  d.Q = in(p.Q, (size_t)(T + 1) * n * n);
+  d.q = in(p.q, (size_t)(T + 1) * n);
+  d.R = in(p.R, (size_t)T * m * m);
+  d.r = in(p.r, (size_t)T * m);
+  d.S = in(p.S, (size_t)T * m * n);
+  d.x0 = in(p.x0, (size_t)n);
+  auto out = [&](void* user, size_t count) -> double* {
+    double* src = q;
+    q += count;
+    if (!user) return nullptr;
+    cout[(*nout)++] = CvtItem{src, user, (int64_t)count, 0, 0};
+    return src;
+  };
+  d.K = out(p.K, (size_t)T * m * n);
+  d.k = out(p.k, (size_t)T * m);
+  d.P = out(p.P, (size_t)(T + 1) * n * n);
+  d.p = out(p.p, (size_t)(T + 1) * n);
+  d.x = out(p.x, (size_t)(T + 1) * n);
+  d.u = out(p.u, (size_t)T * m);
+  d.lam = out(p.lam, (size_t)(T + 1) * n);
+  d.chol = out(p.chol, (size_t)T * m * m);
   return d;
 }
 
@@ -327,7 +403,7 @@ lqr_status_t lqr_workspace_size(const lqr_problem_t* probs, int32_t batch, const
     if (st != LQR_SUCCESS) return st;
     size_t need = plan.total_bytes;
     AdjPlan ap;  // lqr_backward on the same problems uses the same workspace
-    if (make_adj_plan(probs, batch, &ap) == LQR_SUCCESS) need = std::max(need, ap.total_bytes);
+    if (make_adj_plan(probs, batch, &ap, is_f32(opts)) == LQR_SUCCESS) need = std::max(need, ap.total_bytes);
     *bytes = need;
     return LQR_SUCCESS;
   } catch (const std::bad_alloc&) {
@@ -347,11 +423,21 @@ lqr_status_t lqr_solve(const lqr_problem_t* prob, const lqr_options_t* opts, voi
     if ((st = check_device(plan)) != LQR_SUCCESS) return st;
     if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
-    const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int eng = launch_engine(plan.max_n, is_mixed(opts));
-    hipError_t e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
-                                   : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+    const int eng = launch_engine(plan.max_n, is_mixed(opts) || is_f32(opts));
+    InstDesc d;
+    CvtList cin{}, cout{};
+    if (is_f32(opts)) {
+      d = make_desc_f32(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off,
+                        plan.inst[0].stage_off, cin.it, &cin.n, cout.it, &cout.n);
+    } else {
+      d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
+    }
+    hipError_t e = launch_convert_list(cin, s);
+    if (e == hipSuccess)
+      e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
+                          : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+    if (e == hipSuccess) e = launch_convert_list(cout, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;
@@ -362,6 +448,7 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
                              void* ws, size_t ws_bytes, void* stream) {
   try {
     if (phase < 1 || phase > 3) return LQR_ERR_INVALID_ARG;
+    if (is_f32(opts)) return LQR_ERR_UNSUPPORTED;  // phases work on FP64 arrays in place
     BatchPlan plan;
     lqr_status_t st = make_plan(prob, 1, opts, &plan);
     if (st != LQR_SUCCESS) return st;
@@ -420,10 +507,23 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     InstDesc* descs = reinterpret_cast<InstDesc*>(table.data());
     WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + plan.items_off);
     TaskItem* tasks = reinterpret_cast<TaskItem*>(table.data() + plan.tasks_off);
+    const bool f32 = is_f32(opts);
+    CvtItem* cvt = reinterpret_cast<CvtItem*>(table.data() + plan.cvt_off);
+    std::vector<CvtItem> couts;
+    int ncin = 0;
     std::vector<std::pair<double, WorkItem>> order;
     order.reserve(plan.nitems);
     for (int i = 0; i < batch; ++i) {
-      descs[i] = make_desc(probs[i], plan.inst[i].J, base, plan.inst[i].ws_off);
+      if (f32) {
+        CvtItem ci[kMaxCvt], co[kMaxCvt];
+        int ni = 0, no = 0;
+        descs[i] = make_desc_f32(probs[i], plan.inst[i].J, base, plan.inst[i].ws_off,
+                                 plan.inst[i].stage_off, ci, &ni, co, &no);
+        for (int k = 0; k < ni; ++k) cvt[ncin++] = ci[k];
+        couts.insert(couts.end(), co, co + no);
+      } else {
+        descs[i] = make_desc(probs[i], plan.inst[i].J, base, plan.inst[i].ws_off);
+      }
       const lqr_problem_t& p = probs[i];
       const int J = plan.inst[i].J;
       for (int j = 0; j < J; ++j) {
@@ -438,6 +538,8 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
                      });
     for (int i = 0; i < plan.nitems; ++i) items[i] = order[i].second;
     std::copy(plan.tasks.begin(), plan.tasks.end(), tasks);
+    std::copy(couts.begin(), couts.end(), cvt + ncin);
+    const int ncout = (int)couts.size();
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -458,8 +560,10 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + plan.items_off);
     const TaskItem* dtasks = reinterpret_cast<const TaskItem*>(base + plan.tasks_off);
     int32_t* dsync = reinterpret_cast<int32_t*>(base + plan.sync_off);
-    hipError_t e;
-    const int eng = launch_engine(plan.max_n, is_mixed(opts));
+    const CvtItem* dcvt = reinterpret_cast<const CvtItem*>(base + plan.cvt_off);
+    hipError_t e = launch_convert(dcvt, ncin, s);
+    if (e != hipSuccess) return LQR_ERR_HIP;
+    const int eng = launch_engine(plan.max_n, is_mixed(opts) || f32);
     if (serial)
       e = launch_serial_batched(ddesc, batch, plan.max_m, eng, plan.lds_serial, s);
     else if (is_phased(opts))
@@ -469,6 +573,7 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
       e = launch_persistent(ddesc, dtasks, (int)plan.tasks.size(), batch, dsync,
                             kernel_width(plan.max_m, eng), eng,
                             plan.lds_persist, nullptr, s);
+    if (e == hipSuccess) e = launch_convert(dcvt + ncin, ncout, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;
@@ -482,7 +587,8 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
     if (st != LQR_SUCCESS) return st;
     if (!grads) return LQR_ERR_INVALID_ARG;
     AdjPlan ap;
-    if ((st = make_adj_plan(probs, batch, &ap)) != LQR_SUCCESS) return st;
+    const bool f32 = is_f32(opts);
+    if ((st = make_adj_plan(probs, batch, &ap, f32)) != LQR_SUCCESS) return st;
     for (int i = 0; i < batch; ++i) {
       const lqr_problem_t& p = probs[i];
       if (!p.A || !p.B || !p.K || !p.P || !p.x || !p.u || !p.lam || !p.chol) return LQR_ERR_INVALID_ARG;
@@ -494,6 +600,9 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
     std::vector<char> table(ap.table_bytes, 0);
     AdjDesc* descs = reinterpret_cast<AdjDesc*>(table.data());
     int2* blocks = reinterpret_cast<int2*>(table.data() + ap.blocks_off);
+    CvtItem* cvt = reinterpret_cast<CvtItem*>(table.data() + ap.cvt_off);
+    std::vector<CvtItem> couts;
+    int ncin = 0;
     int nb = 0;
     for (int i = 0; i < batch; ++i) {
       const lqr_problem_t& p = probs[i];
@@ -520,9 +629,48 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
       a.dS = static_cast<double*>(g.dS);
       a.dx0 = static_cast<double*>(g.dx0);
       a.ws = reinterpret_cast<double*>(base + ap.ws_off[i]);
+      if (f32) {  // FP64 staging of every array the adjoint reads or writes
+        const size_t t = p.T, t1 = (size_t)p.T + 1, n = p.n, m = p.m;
+        double* q = reinterpret_cast<double*>(base + ap.stage_off[i]);
+        auto in = [&](const void* user, size_t count) -> const double* {
+          double* dst = q;
+          q += count;
+          if (!user) return nullptr;
+          cvt[ncin++] = CvtItem{user, dst, (int64_t)count, 1, 0};
+          return dst;
+        };
+        auto out = [&](void* user, size_t count) -> double* {
+          double* src = q;
+          q += count;
+          if (!user) return nullptr;
+          couts.push_back(CvtItem{src, user, (int64_t)count, 0, 0});
+          return src;
+        };
+        a.A = in(p.A, t * n * n);
+        a.B = in(p.B, t * n * m);
+        a.K = in(p.K, t * m * n);
+        a.P = in(p.P, t1 * n * n);
+        a.chol = in(p.chol, t * m * m);
+        a.x = in(p.x, t1 * n);
+        a.u = in(p.u, t * m);
+        a.lam = in(p.lam, t1 * n);
+        a.dl_dx = in(g.dl_dx, t1 * n);
+        a.dl_du = in(g.dl_du, t * m);
+        a.dA = out(g.dA, t * n * n);
+        a.dB = out(g.dB, t * n * m);
+        a.dc = out(g.dc, t * n);
+        a.dQ = out(g.dQ, t1 * n * n);
+        a.dq = out(g.dq, t1 * n);
+        a.dR = out(g.dR, t * m * m);
+        a.dr = out(g.dr, t * m);
+        a.dS = out(g.dS, t * m * n);
+        a.dx0 = out(g.dx0, n);
+      }
       const int nbi = (p.T + 1 + kAdjStages - 1) / kAdjStages;
       for (int b = 0; b < nbi; ++b) blocks[nb++] = int2{i, b};
     }
+    std::copy(couts.begin(), couts.end(), cvt + ncin);
+    const int ncout = (int)couts.size();
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
@@ -538,8 +686,12 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
           return LQR_ERR_HIP;
       }
     }
-    hipError_t e = launch_adjoint(reinterpret_cast<const AdjDesc*>(base), batch,
-                                  reinterpret_cast<const int2*>(base + ap.blocks_off), nb, ap.lds, s);
+    const CvtItem* dcvt = reinterpret_cast<const CvtItem*>(base + ap.cvt_off);
+    hipError_t e = launch_convert(dcvt, ncin, s);
+    if (e == hipSuccess)
+      e = launch_adjoint(reinterpret_cast<const AdjDesc*>(base), batch,
+                         reinterpret_cast<const int2*>(base + ap.blocks_off), nb, ap.lds, s);
+    if (e == hipSuccess) e = launch_convert(dcvt + ncin, ncout, s);
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
     return LQR_ERR_INVALID_ARG;

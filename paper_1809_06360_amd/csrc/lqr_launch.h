@@ -72,6 +72,11 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
 // states. lds: link_tree_lds of the instance.
 hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream);
 
+// FP32 mode conversions: the arrays of a device table (one block column per
+// array), or a by-value list of one instance's arrays.
+hipError_t launch_convert(const CvtItem* items, int nitems, hipStream_t stream);
+hipError_t launch_convert_list(const CvtList& list, hipStream_t stream);
+
 // Adjoint solve (one workgroup per instance) followed by the gradient
 // outer products (one workgroup per (instance, kAdjStages stages) block).
 hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, int nblocks,

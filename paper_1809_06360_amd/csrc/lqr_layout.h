@@ -51,6 +51,36 @@ struct WorkItem {
   int32_t inst, seg;
 };
 
+// One array conversion between the caller's FP32 buffers and the FP64 staging
+// area of the FP32 precision mode (count elements; to_f64: float -> double,
+// else double -> float).
+struct CvtItem {
+  const void* src;
+  void* dst;
+  int64_t count;
+  int32_t to_f64;
+  int32_t pad_;
+};
+
+// Conversions of one instance, passed by value to single-instance launches:
+// at most 9 inputs (A, B, c, Q, q, R, r, S, x0) or 8 outputs.
+constexpr int kMaxCvt = 9;
+struct CvtList {
+  CvtItem it[kMaxCvt];
+  int32_t n;
+};
+
+// FP64 staging of one instance in the FP32 mode: inputs
+// A | B | c | Q | q | R | r | S | x0, then outputs K | k | P | p | x | u | lam | chol.
+LQR_HD size_t stage_in_doubles(int n, int m, int T) {
+  return (size_t)T * n * n + (size_t)T * n * m + (size_t)T * n + (size_t)(T + 1) * n * n +
+         (size_t)(T + 1) * n + (size_t)T * m * m + (size_t)T * m + (size_t)T * m * n + n;
+}
+LQR_HD size_t stage_out_doubles(int n, int m, int T) {
+  return (size_t)T * m * n + (size_t)T * m + (size_t)(T + 1) * n * n + 3 * (size_t)(T + 1) * n +
+         (size_t)T * m + (size_t)T * m * m;
+}
+
 // A task of the persistent batched launch: phase 1 (segment sweep), 2
 // (linking solve, seg unused) or 3 (rebuild and forward simulation) of one
 // (instance, segment). Tasks are taken from a queue in table order, which the

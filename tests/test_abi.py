@@ -181,13 +181,19 @@ def test_planner_splits_long_single_instances_more_than_short_ones():
 
 
 def test_precision_modes():
-    """FP64 and mixed precision plan the same workspace; FP32 is rejected; the
-    mixed-precision workload (n = 128) does not fit the LDS-resident kernels."""
+    """FP64 and mixed precision plan the same workspace; FP32 adds the staging
+    area; the mixed-precision workload (n = 128) does not fit the kernels."""
     a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("fp64"))
     b = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("mixed"))
     assert a == b
-    with pytest.raises(L.LQRError) as e:
-        L.lqr_workspace_size(ctypes.byref(_prob(16, 8, 128, 0)), 1, L.options("fp32"))
+    # FP32 stages the float arrays as doubles in the workspace
+    c = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("fp32"))
+    assert c > a
+    prob = _prob(4, 2, 8, 2)
+    for name in ("A", "B", "c", "Q", "q", "R", "r", "x0", "K", "k", "x", "u", "info"):
+        setattr(prob, name, 256)
+    with pytest.raises(L.LQRError) as e:     # the phase-by-phase entry works on FP64 arrays
+        L.lqr_solve_phase(prob, L.options("fp32"), 1, 256, 1 << 30, 0)
     assert e.value.status == L.ERR_UNSUPPORTED
     from synthetic import WORKLOADS
     (n, m, T), = WORKLOADS["mixed"].dims

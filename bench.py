@@ -394,47 +394,47 @@ def run_diff(args, w):
     probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
     datas = [{k: torch.from_numpy(v).to(dev) for k, v in p.items()} for p in probs]
     keys = ("A", "B", "c", "Q", "q", "R", "r", "x0")
-    outs, ws = L.solve_batched(datas, with_chol=True)
-    gx = [2.0 * o["x"] for o in outs]
-    gu = [2.0 * o["u"] for o in outs]
-    grads = L.backward(datas, outs, gx, gu, which=keys)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    for _ in range(args.warmup):
-        L.solve_batched(datas, outputs=outs, workspace=ws)
-        L.backward(datas, outs, gx, gu, which=keys, workspace=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s_ in range(K):
-        ev[s_][0].record(stream)
-        L.solve_batched(datas, outputs=outs, workspace=ws)
-        ev[s_][1].record(stream)
-        L.backward(datas, outs, gx, gu, which=keys, workspace=ws)
-        ev[s_][2].record(stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / K
-    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    bwd = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+
+    def graphs(ds, precision):
+        """Forward and adjoint calls captured in two graphs (each with its own
+        workspace, whose plan the eager calls upload), so the timed region is
+        device work only."""
+        outs, ws_f = L.solve_batched(ds, precision=precision, with_chol=True)
+        gx = [2.0 * o["x"] for o in outs]
+        gu = [2.0 * o["u"] for o in outs]
+        gs = L.backward(ds, outs, gx, gu, which=keys)
+        ws_b = gs[0]["_workspace"]
+        torch.cuda.synchronize()
+        gf, gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gf):
+            L.solve_batched(ds, outputs=outs, workspace=ws_f, precision=precision)
+        with torch.cuda.graph(gb):
+            L.backward(ds, outs, gx, gu, which=keys, workspace=ws_b, outputs=gs)
+        for _ in range(args.warmup):
+            gf.replay()
+            gb.replay()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        t0 = time.perf_counter()
+        for s_ in range(K):
+            ev[s_][0].record(stream)
+            gf.replay()
+            ev[s_][1].record(stream)
+            gb.replay()
+            ev[s_][2].record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / K
+        f = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        b = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        return wall, f, b
+
+    ms, fwd, bwd = graphs(datas, "fp64")
     # the same in the FP32 precision mode (float arrays; float matrix-core
     # products, double factorizations; adjoint in double on staged arrays)
     d32 = [{k: v.float() for k, v in d.items()} for d in datas]
-    o32, ws32 = L.solve_batched(d32, precision="fp32", with_chol=True)
-    gx32 = [2.0 * o["x"] for o in o32]
-    gu32 = [2.0 * o["u"] for o in o32]
-    L.backward(d32, o32, gx32, gu32, which=keys)
-    torch.cuda.synchronize()
-    ev32 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    for s_ in range(K):
-        ev32[s_][0].record(stream)
-        L.solve_batched(d32, outputs=o32, workspace=ws32, precision="fp32")
-        ev32[s_][1].record(stream)
-        L.backward(d32, o32, gx32, gu32, which=keys, workspace=ws32)
-        ev32[s_][2].record(stream)
-    torch.cuda.synchronize()
-    fwd32 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev32]))
-    bwd32 = float(np.mean([e[1].elapsed_time(e[2]) for e in ev32]))
+    _, fwd32, bwd32 = graphs(d32, "fp32")
     log("fp64 forward %.3f ms backward %.3f ms; fp32 forward %.3f ms backward %.3f ms"
         % (fwd, bwd, fwd32, bwd32))
     n, m, T = w.dims[0]

@@ -187,7 +187,9 @@ lqr_status_t lqr_plan_segments(const lqr_problem_t *probs, int32_t batch,
 
 /* Solve `batch` independent instances of possibly different n, m, T.
  * With LQR_ALGO_PARALLEL (and no LQR_FLAG_PHASED) this is ONE persistent
- * launch (after a small kernel that clears its counters): resident
+ * launch (after a small kernel that clears its counters; when every instance
+ * has one segment, the same plain one-workgroup-per-instance launch as
+ * LQR_ALGO_SERIAL, which that case reduces to): resident
  * workgroups take tasks -- segment sweeps, linking solves, rebuilds -- from a
  * queue in an order fixed by the planner, and per-instance counters in the
  * workspace make each linking solve wait for its instance's sweeps and each

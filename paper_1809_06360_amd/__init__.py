@@ -273,11 +273,13 @@ GRAD_KEYS = ("A", "B", "c", "Q", "q", "R", "r", "S", "x0")
 
 
 def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=None,
-             precision: str = None):
+             precision: str = None, outputs=None):
     """Gradients of a loss l(x, u) with respect to the problem data of a batch
     already solved by ``solve_batched`` (``outs`` must hold K, P, x, u, lam,
     chol). ``dl_dx[i]``, ``dl_du[i]``: upstream gradients of instance i.
-    Returns a list of dicts of gradient tensors (keys in ``which``)."""
+    Returns a list of dicts of gradient tensors (keys in ``which``); ``outputs``:
+    such a list from an earlier call to write into (needed to replay the call in
+    a captured graph, whose plan holds the output addresses)."""
     import torch
     batch = len(datas)
     probs = (LqrProblem * batch)()
@@ -293,7 +295,7 @@ def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=
         z = lambda *s: torch.empty(*s, dtype=data["A"].dtype, device=data["A"].device)  # noqa: E731
         shapes = dict(A=(T, n, n), B=(T, n, m), c=(T, n), Q=(T + 1, n, n), q=(T + 1, n),
                       R=(T, m, m), r=(T, m), S=(T, m, n), x0=(n,))
-        g = {k: z(*shapes[k]) for k in which}
+        g = outputs[i] if outputs is not None else {k: z(*shapes[k]) for k in which}
         res.append(g)
         gx, gu = dl_dx[i].contiguous(), dl_du[i].contiguous()
         g["_keep"] = (gx, gu)

@@ -564,7 +564,11 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     hipError_t e = launch_convert(dcvt, ncin, s);
     if (e != hipSuccess) return LQR_ERR_HIP;
     const int eng = launch_engine(plan.max_n, is_mixed(opts) || f32);
-    if (serial)
+    // With one segment per instance the parallel algorithm is the plain
+    // recursion; one workgroup per instance runs it without the task queue.
+    bool single = true;
+    for (int i = 0; i < batch && single; ++i) single = plan.inst[i].J == 1;
+    if (serial || (single && !is_phased(opts)))
       e = launch_serial_batched(ddesc, batch, plan.max_m, eng, plan.lds_serial, s);
     else if (is_phased(opts))
       e = launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n, plan.max_m,

@@ -66,8 +66,9 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
   }
   const double* b = scan_elem(const_cast<double*>(in), n, j + dist);
   const bool exact_b = j + 2 * dist - 1 >= J - 1;
-  const double *P0a = a, *Ga = a + nn, *Psa = a + 2 * nn, *pa = a + 3 * nn, *psa = pa + n;
-  const double *P0b = b, *Gb = b + nn, *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
+  const double *P0a = a, *pa = a + 3 * nn, *psa = pa + n;
+  const double *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
+  const double *Ga = a + nn, *Psa = a + 2 * nn, *P0b = b, *Gb = b + nn;
   const int mp = MN + 1;
   const int nc = exact_b ? 2 * n + 1 : 3 * n + 1;
   double* sN = smem;                     // mp x nc column-major: [M | RHS] -> [. | X1 | x2 | X3]
@@ -76,6 +77,20 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
   double* gjb = sv + n;
   int* prow = reinterpret_cast<int*>(gjb + 3 * MN + 2);
   int* flag = prow + MN;
+  if constexpr (link_tree_staged(MN)) {
+    // the four n x n operands of the products, staged in LDS by coalesced loads
+    double* st = reinterpret_cast<double*>(flag + 4);
+    double *sGa = st, *sPsa = st + nn, *sP0b = st + 2 * nn, *sGb = st + 3 * nn;
+    load_block(sGa, n, Ga, n, n, n);
+    load_block(sPsa, n, Psa, n, n, n);
+    load_block(sP0b, n, P0b, n, n, n);
+    if (!exact_b) load_block(sGb, n, Gb, n, n, n);
+    Ga = sGa;
+    Psa = sPsa;
+    P0b = sP0b;
+    Gb = sGb;
+    __syncthreads();
+  }
   if (threadIdx.x == 0) flag[0] = 0;
   constexpr int E64 = fp64_engine(E);
   pgemm_sub<E64, false, false, false, false>(n, n, n, P0b, n, Psa, n, 0, P0b, n, Psa, n,

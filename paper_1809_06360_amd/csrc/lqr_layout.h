@@ -210,9 +210,14 @@ LQR_HD constexpr int persist_nw(bool mf) { return mf ? 64 : 32; }
 // Join of two summaries: [M | RHS] mp x (3n+1) column-major, Psi_a Gam_b
 // (n x n), a vector, Gauss-Jordan exchange and pivots (the link-map kernel
 // uses less).
+// Up to this register width the join also stages its four n x n product
+// operands in LDS (they fit next to the elimination block).
+LQR_HD constexpr bool link_tree_staged(int nw) { return nw <= 48; }
+
 LQR_HD size_t link_tree_lds(int n, int nw) {
   const size_t mx = (size_t)nw, mp = mx + 1;
-  const size_t dbl = mp * (3 * (size_t)n + 1) + (size_t)n * n + n + 3 * mx + 2;
+  size_t dbl = mp * (3 * (size_t)n + 1) + (size_t)n * n + n + 3 * mx + 2;
+  if (link_tree_staged(nw)) dbl += 4 * (size_t)n * n + 1;
   return dbl * 8 + (mx + 4) * 4 + 64;
 }
 

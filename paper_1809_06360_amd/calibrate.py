@@ -9,7 +9,7 @@ events (median of repeated launches on one stream):
   phase 1 with J = 1       -> T plain Riccati stages      -> cost per plain stage
   phase 3 with J = 1       -> T forward-simulation stages -> cost per rollout stage
   phase 1 with J = 8       -> T/8 parametric stages       -> cost per dual stage
-  phase 2 with J = 8, 32   -> 7 and 31 linking steps      -> cost per linking step
+  phase 2 with J = 2, 7    -> 1 and 6 serial linking steps -> cost per linking step
 and fits each cost, separately for the VALU (n < 32) and matrix-core
 (n >= 32) kernel variants, as a non-negative combination of the features
 named in the generated header.
@@ -26,7 +26,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 T_CAL = 64
-NS = (4, 8, 12, 16, 24, 31, 32, 40, 48, 56, 64)
+NS = (4, 8, 12, 16, 24, 31, 32, 40, 48, 52, 56, 60, 64)
 MS = (2, 4, 8, 16, 24, 32)
 
 
@@ -43,6 +43,16 @@ def pad_rows(m):
         if m <= w:
             return w
     return 64
+
+
+def streamed(n, m):
+    """Whether phase 1 runs the streamed parametric sweep for this size (the
+    resident layout of a width-w kernel exceeds 160 KiB of LDS; matrix-core
+    kernels use widths of at least 16)."""
+    w = pad_rows(max(m, 9) if n >= 32 else m)
+    W = m + 2 * n + 1
+    dbl = n * n + n + n * (m + n + 1) + n * W + (w + 1) * W + 3 * w + n * n + 2 * n
+    return dbl * 8 + 64 > 160 * 1024
 
 
 def _instance(n, m, T, rng):
@@ -86,14 +96,17 @@ def measure(L, torch):
         for m in MS:
             host = _instance(n, m, T_CAL, rng)
             data = {k: torch.from_numpy(v).cuda() for k, v in host.items()}
-            row = dict(n=n, m=m, mw=pad_rows(m), mf=int(n >= 32))
+            row = dict(n=n, m=m, mw=pad_rows(max(m, 9) if n >= 32 else m), mf=int(n >= 32),
+                       gs=int(streamed(n, m)))
             row["plain"] = 1e3 * time_phase(L, torch, data, 1, 1) / T_CAL
             row["roll"] = 1e3 * time_phase(L, torch, data, 1, 3) / T_CAL
             try:
                 row["dual"] = 1e3 * time_phase(L, torch, data, 8, 1) / (T_CAL // 8)
-                t8 = time_phase(L, torch, data, 8, 2)
-                t32 = time_phase(L, torch, data, 32, 2)
-                row["link"] = 1e3 * (t32 - t8) / 24.0
+                # the serial linking chain (single instances link J < 8
+                # segments serially; batched launches always do)
+                t2 = time_phase(L, torch, data, 2, 2)
+                t7 = time_phase(L, torch, data, 7, 2)
+                row["link"] = 1e3 * (t7 - t2) / 5.0
             except L.LQRError:
                 row["dual"] = row["link"] = None  # cannot be split on this device
             rows.append(row)
@@ -106,7 +119,7 @@ def measure(L, torch):
 
 def features(kind, r):
     n, m, mw = r["n"], r["m"], r["mw"]
-    if kind == "dual":
+    if kind in ("dual", "dualgs"):
         return [1.0, mw, n, flops_dual(n, m) / 1e5]
     if kind == "plain":
         return [1.0, mw, n, flops_plain(n, m) / 1e5]
@@ -118,10 +131,19 @@ def features(kind, r):
 def fit(rows):
     from scipy.optimize import nnls
     coef = {}
-    for kind in ("dual", "plain", "roll", "link"):
+    for kind in ("dual", "dualgs", "plain", "roll", "link"):
         coef[kind] = []
         for mf in (0, 1):
-            sel = [r for r in rows if r["mf"] == mf and r.get(kind) is not None]
+            if kind == "dualgs":
+                sel = [dict(r, dualgs=r["dual"]) for r in rows
+                       if r["mf"] == mf and r["gs"] and r.get("dual") is not None]
+                if not sel:  # no streamed sizes for this engine
+                    coef[kind].append(np.zeros(4))
+                    continue
+            elif kind == "dual":
+                sel = [r for r in rows if r["mf"] == mf and not r["gs"] and r.get(kind) is not None]
+            else:
+                sel = [r for r in rows if r["mf"] == mf and r.get(kind) is not None]
             if kind == "link":  # one row per n
                 seen = {}
                 for r in sel:
@@ -145,7 +167,7 @@ HEADER = """// Per-stage cost model of the solver kernels on MI355X (microsecond
 // phase timings with HIP events, T = {T} stages, non-negative least squares).
 //
 // Each cost is a non-negative combination of features (see lqr_tuner.cpp):
-//   sweeps (dual, plain)  [1, mw, n, flops / 1e5]
+//   sweeps (dual, dual streamed, plain)  [1, mw, n, flops / 1e5]
 //   rollout               [1, n, m, n (n + m) / 1e3]
 //   link                  [1, n, n^2 / 1e2, n^3 / 1e4]
 // indexed [mf][feature], mf = 1 for the matrix-core product variants.
@@ -164,7 +186,8 @@ constexpr double kTask = 3.0;
 
 def render(coef):
     lines = []
-    for kind, name in (("dual", "kDual"), ("plain", "kPlain"), ("roll", "kRoll"), ("link", "kLink")):
+    for kind, name in (("dual", "kDual"), ("dualgs", "kDualStreamed"), ("plain", "kPlain"),
+                       ("roll", "kRoll"), ("link", "kLink")):
         rows = ", ".join("{%s}" % ", ".join("%.6g" % v for v in c) for c in coef[kind])
         lines.append("constexpr double %s[2][4] = {%s};" % (name, rows))
     return HEADER.format(T=T_CAL, body="\n".join(lines))

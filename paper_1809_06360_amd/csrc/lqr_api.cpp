@@ -108,12 +108,10 @@ lqr_status_t check_pointers(const lqr_problem_t& p) {
   return LQR_SUCCESS;
 }
 
-// Resident workgroups the tuner plans for: up to two per compute unit, as the
-// LDS footprint allows.
-int planned_slots(size_t lds) {
-  const size_t per_cu = std::max<size_t>(1, std::min<size_t>(2, kLdsGfx950 / std::max<size_t>(lds, 1)));
-  return (int)per_cu * kComputeUnits;
-}
+// Resident workgroups the tuner plans for: one per compute unit. The
+// persistent kernel holds every task type, which takes more than 256 VGPRs
+// per lane, so one 256-thread workgroup fills a compute unit whatever its LDS.
+int planned_slots(size_t /*lds*/) { return kComputeUnits; }
 
 lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
                         BatchPlan* plan) {

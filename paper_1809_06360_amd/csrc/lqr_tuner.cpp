@@ -35,7 +35,9 @@ StageCost stage_cost(int n, int m, int mw, bool mf) {
   const int e = mf ? 1 : 0;
   const double fp = flops_plain(n, m), fd = fp + flops_dual_extra(n, m);
   StageCost c;
-  c.dual = dot4(cost::kDual[e], 1.0, mw, n, fd / 1e5);
+  // segments whose resident layout exceeds the LDS run the streamed sweep
+  const bool gs = sweep_lds(n, m, true, mw) > kLdsSweepMax;
+  c.dual = dot4(gs ? cost::kDualStreamed[e] : cost::kDual[e], 1.0, mw, n, fd / 1e5);
   c.plain = dot4(cost::kPlain[e], 1.0, mw, n, fp / 1e5);
   c.roll = dot4(cost::kRoll[e], 1.0, n, m, (double)n * (n + m) / 1e3);
   c.link = dot4(cost::kLink[e], 1.0, n, (double)n * n / 1e2, (double)n * n * n / 1e4);

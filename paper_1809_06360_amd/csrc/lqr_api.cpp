@@ -125,6 +125,8 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
     if ((st = check_dims(p)) != LQR_SUCCESS) return st;
+    // register-resident columns and rows of the kernels (elimination, simulation)
+    if (p.n > 64 || p.m > 64) return LQR_ERR_UNSUPPORTED;
     plan->max_n = std::max(plan->max_n, p.n);
     plan->max_m = std::max(plan->max_m, p.m);
   }

@@ -62,6 +62,61 @@ LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual, int mw) {
   return s;
 }
 
+// Cache warming for the next stage of a backward sweep: one double of every
+// 128-byte line of stage t's inputs (A, B, c, Q, q, R, r, S), up to
+// kTouch * kThreads lines, is loaded into registers. Issued right after a
+// stage's own inputs are staged, the loads complete while that stage
+// computes; sink() stores their sum to a dead LDS word at the end of the
+// stage, so the wait for them lands where nothing is pending.
+constexpr int kTouch = 6;
+struct Touch {
+  double v[kTouch];
+};
+
+LQR_DEV Touch touch_stage(const InstDesc& d, int t) {
+  const int n = d.n, m = d.m;
+  const double* base[8] = {d.A + (size_t)t * n * n, d.B + (size_t)t * n * m, d.c + (size_t)t * n,
+                           d.Q + (size_t)t * n * n, d.q + (size_t)t * n,     d.R + (size_t)t * m * m,
+                           d.r + (size_t)t * m,     d.S ? d.S + (size_t)t * m * n : d.r};
+  const int cnt[8] = {n * n, n * m, n, n * n, n, m * m, m, d.S ? m * n : 0};
+  Touch h;
+#pragma unroll
+  for (int k = 0; k < kTouch; ++k) {
+    int g = threadIdx.x + k * kThreads;  // line index over the concatenated arrays
+    const double* p = nullptr;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int lines = (cnt[a] + 15) >> 4;
+      if (!p && g < lines) p = base[a] + 16 * g;
+      if (!p) g -= lines;
+    }
+    h.v[k] = p ? *p : 0.0;
+  }
+  return h;
+}
+
+LQR_DEV void sink(const Touch& h, double* dead) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < kTouch; ++k) a += h.v[k];
+  *dead = a;
+}
+
+// sum_k M[k * ldm + i] v[k * ldv] for k < n: four independent partial sums,
+// so that the loads of several k are in flight at once.
+LQR_DEV double col_dot(const double* M, int ldm, const double* v, int ldv, int i, int n) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    a0 = fma(M[k * ldm + i], v[k * ldv], a0);
+    a1 = fma(M[(k + 1) * ldm + i], v[(k + 1) * ldv], a1);
+    a2 = fma(M[(k + 2) * ldm + i], v[(k + 2) * ldv], a2);
+    a3 = fma(M[(k + 3) * ldm + i], v[(k + 3) * ldv], a3);
+  }
+  for (; k < n; ++k) a0 = fma(M[k * ldm + i], v[k * ldv], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
 // Stage inputs into LDS: X = [B_t | A_t | c_t].
 LQR_DEV void load_stage(const InstDesc& d, int t, const SweepLds& s) {
   const int n = d.n, m = d.m;
@@ -152,8 +207,10 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
   load_block(s.P, n, Pend, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) s.p[i] = pend[i];
   int fail = 0;
+  double* dead = reinterpret_cast<double*>(s.bad) + 1;
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
+    const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     stage_products<MM, E>(d, s);
     __syncthreads();
@@ -178,6 +235,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
               kt[i] = v;
           });
     }
+    sink(next, dead);
     __syncthreads();
   }
   return fail;
@@ -205,17 +263,15 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
     s.psi[i] = 0.0;
   }
   int fail = 0;
+  double* dead = reinterpret_cast<double*>(s.bad) + 1;
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
+    const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     stage_products<MM, E>(d, s);
     {  // gc = Gam' c_t (Gam of stage t+1)
       const double* X = s.X;
-      for (int i = threadIdx.x; i < n; i += kThreads) {
-        double a = 0.0;
-        for (int k = 0; k < n; ++k) a = fma(Gam[k * W + i], X[k * WX + m + n], a);
-        s.gc[i] = a;
-      }
+      for (int i = threadIdx.x; i < n; i += kThreads) s.gc[i] = col_dot(Gam, W, X + m + n, WX, i, n);
     }
     __syncthreads();
     stage_hessian<MM, E>(d, t, s, W);
@@ -253,6 +309,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
       const int i = e / n, j = e - i * n;
       Gam[i * W + j] = s.Y[i * W + m + j];
     }
+    sink(next, dead);
   }
   __syncthreads();
   const int nn = n * n;
@@ -306,6 +363,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     const double* rt = d.r + (size_t)t * m;
     load_block(X, WX, d.B + (size_t)t * n * m, m, n, m);
     for (int i = threadIdx.x; i < n; i += kThreads) X[i * WX + m] = ct[i];
+    const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     // Y = P [B | A | c] + [0 | 0 | p]
     pgemm_sub<E, false, false, false, false>(n, m + 1, n, P, n, X, WX, 0, P, n, X, WX,
@@ -315,11 +373,8 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
         });
     pgemm_sub<E, false, false, false, false>(n, n, n, P, n, At, n, 0, P, n, At, n,
         [=](int i, int j, double v) { Y[i * WY + m + j] = v; });
-    for (int i = threadIdx.x; i < n; i += kThreads) {  // gc = Gam' c (Gam of stage t+1)
-      double a = 0.0;
-      for (int k = 0; k < n; ++k) a = fma(Gam[k * n + i], X[k * WX + m], a);
-      gc[i] = a;
-    }
+    // gc = Gam' c (Gam of stage t+1)
+    for (int i = threadIdx.x; i < n; i += kThreads) gc[i] = col_dot(Gam, n, X + m, WX, i, n);
     __syncthreads();
     // G = B'[PB | PA | Pc+p | Gam] + [R | S | r | 0]
     pgemm_sub<E, true, false, false, false>(m, m + n + 1, n, X, WX, Y, WY, 0, X, WX, Y, WY,
@@ -370,6 +425,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     // Gam <- A'Gam - Z_ux'Z_W into the other buffer
     pgemm_sub<E, true, false, false, true>(n, n, n, At, n, Gam, n, m, G + m * mp, mp,
         G + (m + n + 1) * mp, mp, [=](int i, int j, double v) { Gn[i * n + j] = v; });
+    sink(next, reinterpret_cast<double*>(bad) + 1);
     __syncthreads();
     double* tmp = Gam;
     Gam = Gn;
@@ -386,50 +442,112 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
   return fail;
 }
 
+// Rows `lane` of the column block [c0, c0 + cw) of an M (rows x cols, row
+// stride ld) into registers r[0..15]; zero outside the matrix.
+LQR_DEV void load_row_block(double (&r)[16], const double* M, int ld, int rows, int cols, int c0, int cw,
+                            int lane) {
+  const bool ok = lane < rows;
+  const double* row = M + (size_t)(ok ? lane : 0) * ld + c0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) r[q] = (ok && q < cw && c0 + q < cols) ? row[q] : 0.0;
+}
+
+// s + sum_q r[q] v_{c0+q} for q < cw, where v_c is held by lane c of the wave
+// (c0 and cw wave-uniform, c0 + cw <= 64).
+LQR_DEV double row_block_dot(const double (&r)[16], double v, int c0, int cw, double s) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q < cw) s = fma(r[q], readlane(v, c0 + q), s);
+  return s;
+}
+
 // Forward simulation of stages [t0, t1) from x_{t0} = xs (global):
 // u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t; writes x_t, u_t
 // (and lam_t = P_t x_t + p_t when requested), plus x_T (lam_T) if last.
+// n, m <= 64. Every wave holds the state in registers (lane i: x_i, u_i).
+// Each matrix-vector product is split by columns over the waves (wave w takes
+// a contiguous quarter of the columns, lane i row i); the partial sums meet in
+// LDS and every wave adds them up in the same order, so a stage costs two
+// barriers. The next stage's matrix rows are loaded into registers while the
+// current stage is computed, which keeps global-memory latency off the chain.
+// LDS: rollout_lds.
 LQR_DEV void rollout(const InstDesc& d, int t0, int t1, const double* xs, bool last, double* smem) {
-  const int n = d.n, m = d.m;
-  double* sx = smem;
-  double* sxn = smem + n;
-  double* su = smem + 2 * n;
-  for (int i = threadIdx.x; i < n; i += kThreads) sx[i] = xs[i];
-  __syncthreads();
+  const int n = d.n, m = d.m, T = d.T;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cn = (n + kWaves - 1) / kWaves, cm = (m + kWaves - 1) / kWaves;
+  const int n0 = wave * cn, m0 = wave * cm;
+  const bool rn = lane < n, rm = lane < m;
+  const bool want_lam = d.lam != nullptr;
+  double* part1 = smem;                 // [kWaves][128]: P x rows in [0, 64), K x rows in [64, 128)
+  double* part2 = smem + kWaves * 128;  // [kWaves][64]: A x + B u
+  double pP[16], pK[16], pA[16], pB[16];
+  double bp = 0.0, bk = 0.0, bc = 0.0;  // p_t, k_t, c_t of row `lane`
+#pragma unroll
+  for (int q = 0; q < 16; ++q) pP[q] = pK[q] = pA[q] = pB[q] = 0.0;
+  // value (P_t, p_t), gain (K_t, k_t) and dynamics (A_t, B_t, c_t) of stage t
+  auto fetch_value = [&](int t) {
+    load_row_block(pP, d.P + (size_t)t * n * n, n, n, n, n0, cn, lane);
+    bp = rn ? d.p[(size_t)t * n + lane] : 0.0;
+  };
+  auto fetch_gain = [&](int t) {
+    load_row_block(pK, d.K + (size_t)t * m * n, n, m, n, n0, cn, lane);
+    bk = rm ? d.k[(size_t)t * m + lane] : 0.0;
+  };
+  auto fetch_dyn = [&](int t) {
+    load_row_block(pA, d.A + (size_t)t * n * n, n, n, n, n0, cn, lane);
+    load_row_block(pB, d.B + (size_t)t * n * m, m, n, m, m0, cm, lane);
+    bc = rn ? d.c[(size_t)t * n + lane] : 0.0;
+  };
+  double x = rn ? xs[lane] : 0.0, u = 0.0;
+  if (t0 < t1) {
+    if (want_lam) fetch_value(t0);
+    fetch_gain(t0);
+    fetch_dyn(t0);
+  } else if (last && want_lam) {
+    fetch_value(T);
+  }
   for (int t = t0; t < t1; ++t) {
-    double* xt = d.x + (size_t)t * n;
-    for (int i = threadIdx.x; i < n; i += kThreads) xt[i] = sx[i];
-    if (d.lam) {
-      const double* pt = d.p + (size_t)t * n;
-      double* lt = d.lam + (size_t)t * n;
-      gemv2(n, n, d.P + (size_t)t * n * n, n, sx, 0, sx, 0, sx,
-            [=](int i, double v) { lt[i] = pt[i] + v; });
+    const bool more = t + 1 < t1;
+    if (wave == 0 && rn) d.x[(size_t)t * n + lane] = x;
+    // partial P x and K x over this wave's columns
+    part1[wave * 128 + lane] = want_lam ? row_block_dot(pP, x, n0, cn, 0.0) : 0.0;
+    part1[wave * 128 + 64 + lane] = row_block_dot(pK, x, n0, cn, 0.0);
+    const double cp = bp, ck = bk;
+    if (want_lam && (more || last)) fetch_value(t + 1);
+    if (more) fetch_gain(t + 1);
+    __syncthreads();
+    double sl = 0.0, su = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      sl += part1[w * 128 + lane];
+      su += part1[w * 128 + 64 + lane];
     }
-    const double* kt = d.k + (size_t)t * m;
-    double* ut = d.u + (size_t)t * m;
-    gemv2(m, n, d.K + (size_t)t * m * n, n, sx, 0, sx, 0, sx, [=](int i, double v) {
-      v += kt[i];
-      su[i] = v;
-      ut[i] = v;
-    });
+    if (want_lam && wave == 2 && rn) d.lam[(size_t)t * n + lane] = cp + sl;
+    u = rm ? ck + su : 0.0;
+    if (wave == 1 && rm) d.u[(size_t)t * m + lane] = u;
+    // partial A x + B u
+    part2[wave * 64 + lane] = row_block_dot(pB, u, m0, cm, row_block_dot(pA, x, n0, cn, 0.0));
+    const double cb = bc;
+    if (more) fetch_dyn(t + 1);
     __syncthreads();
-    const double* ct = d.c + (size_t)t * n;
-    gemv2(n, n, d.A + (size_t)t * n * n, n, sx, m, d.B + (size_t)t * n * m, m, su,
-          [=](int i, double v) { sxn[i] = ct[i] + v; });
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kThreads) sx[i] = sxn[i];
-    __syncthreads();
+    double sx = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) sx += part2[w * 64 + lane];
+    x = rn ? cb + sx : 0.0;
   }
   if (last) {
-    double* xT = d.x + (size_t)d.T * n;
-    for (int i = threadIdx.x; i < n; i += kThreads) xT[i] = sx[i];
-    if (d.lam) {
-      const double* pT = d.p + (size_t)d.T * n;
-      double* lT = d.lam + (size_t)d.T * n;
-      gemv2(n, n, d.P + (size_t)d.T * n * n, n, sx, 0, sx, 0, sx,
-            [=](int i, double v) { lT[i] = pT[i] + v; });
+    if (wave == 0 && rn) d.x[(size_t)T * n + lane] = x;
+    if (want_lam) {
+      part1[wave * 128 + lane] = row_block_dot(pP, x, n0, cn, 0.0);
+      __syncthreads();
+      double sl = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) sl += part1[w * 128 + lane];
+      if (wave == 2 && rn) d.lam[(size_t)T * n + lane] = bp + sl;
     }
   }
+  __syncthreads();
 }
 
 // Terminal value P_T = Q_T, p_T = q_T into the outputs (if requested).

@@ -221,8 +221,8 @@ LQR_HD size_t link_tree_lds(int n, int nw) {
   return dbl * 8 + (mx + 4) * 4 + 64;
 }
 
-// Forward simulation: x_t and x_{t+1} (n each), u_t (m).
-LQR_HD size_t rollout_lds(int n, int m) { return (2 * (size_t)n + m) * 8 + 64; }
+// Partial sums of the forward simulation's matrix-vector products (n, m <= 64).
+LQR_HD size_t rollout_lds(int /*n*/, int /*m*/) { return (4 * 128 + 4 * 64) * 8 + 64; }
 
 // `nw` is the register width of the kernel variant (pad_rows of the largest n).
 LQR_HD size_t couple_lds(int n, int nw) {

@@ -209,83 +209,107 @@ LQR_HD int pad_m(int m) { return pad_rows(m); }
 LQR_HD int pad_ld(int m) { return pad_rows(m) + 1; }
 
 // ---------------------------------------------------------------------------
-// Square-root-free Cholesky (L D L') of the m x m input Hessian H, carried out
-// as forward elimination on a set of right-hand sides. Thread c owns "virtual
-// column" c in registers: [0, m) = the columns of H, [m, m + nr) = right-hand
-// sides (the same columns of G), and, if `ident`, [m + nr, 2m + nr) = the
-// identity (not stored in G). G is column-major in LDS with leading dimension
-// ldg. Round k (m rounds, one barrier each): the owner of H's column k
-// publishes the pivot d_k and the multipliers H(i, k)/d_k (i > k) to a
-// double-buffered LDS vector; every column c > k of H and every right-hand
-// side then updates its rows i > k with its own row-k entry. The round loop is
-// unrolled for m <= MAXM so all register indices are compile-time.
+// Square-root-free Cholesky (L D L') of the m x m input Hessian H and forward
+// elimination of a set of right-hand sides. G is column-major in LDS with
+// leading dimension ldg: columns [0, m) hold H, [m, m + nr) the right-hand
+// sides; if `ident`, m more right-hand sides are the identity (not stored).
+//  1. Wave 0 factors H with lane k holding column k in registers. In round k
+//     every lane reads the pivot d_k and column k from lane k (readlane) and
+//     lane c > k updates its rows i > k by -H(i, k) H(k, c) / d_k: the trailing
+//     block stays symmetric, so lane c's own row-k entry is H(k, c). No
+//     barrier inside the factorization. Lane k then stores the multipliers
+//     H(i, k)/d_k (i > k) over H's column k in G and 1/sqrt(d_k) to buf.
+//  2. Every right-hand side (one thread per column) runs the unit-lower
+//     forward substitution with those multipliers and scales row i by
+//     1/sqrt(d_i).
+// The loops are unrolled for m <= MAXM so every register index is fixed.
 //
 // On return (ends with a barrier):
 //   Z = L^{-1} X  for every right-hand side X (L = L_unit D^{1/2} the
 //     Cholesky factor), written to G's columns [m, m + nr);
 //   if ident: L^{-1} written to zi (column q of L^{-1} at zi + q * ldzi);
-//   if chol != nullptr: L written row-major to chol (m x m, zeros above).
+//   if chol != nullptr: L written row-major to chol (m x m, zeros above);
+//   G's columns [0, m) hold the multipliers (unless zi overwrote them).
 // A pivot that is not positive or not finite is replaced by NaN (which then
 // propagates into every dependent result) and *bad is set to 1.
-// buf: 3 * MAXM doubles of LDS. Requires 2m + nr (or m + nr) <= 256 and a
-// barrier between G's producer and this call.
+// buf: MAXM doubles of LDS. Requires m <= 64, m + nr + (ident ? m : 0) <= 256
+// and a barrier between G's producer and this call.
 // ---------------------------------------------------------------------------
 template <int MAXM>
 LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* zi, int ldzi,
                          double* chol, double* buf, int* bad) {
-  // Rows m..MAXM-1 are zero padding, so the unrolled round body needs no
-  // per-element guards: padded multipliers are zero and padded rows stay zero.
   const int c = threadIdx.x;
-  const int nvc = m + nr + (ident ? m : 0);
-  const bool own = c < nvc;
-  const bool isH = c < m;
-  const bool fromG = c < m + nr;
-  const int q = c - m - nr;
-  const double* src = G + (fromG ? c : 0) * ldg;
-  double* piv = buf + 2 * MAXM;
-  double v[MAXM];
+  const int lane = c & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(c >> 6);
+  if (wave == 0) {
+    // rows m..MAXM-1 and lanes m..63 are zero padding: they stay zero
+    double v[MAXM];
+    const bool isH = lane < m;
+    const double* src = G + (isH ? lane : 0) * ldg;
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    const double g = src[i];
-    v[i] = (own && i < m) ? (fromG ? g : (i == q ? 1.0 : 0.0)) : 0.0;
-  }
+    for (int i = 0; i < MAXM; ++i) v[i] = (isH && i < m) ? src[i] : 0.0;
+    int badf = 0;
 #pragma unroll
-  for (int k = 0; k < MAXM; ++k) {
-    if (k < m) {
-      double* cb = buf + (k & 1) * MAXM;
-      if (c == k) {
-        double dk = v[k];
+    for (int k = 0; k < MAXM; ++k) {
+      if (k < m) {
+        double dk = readlane(v[k], k);
         if (!(dk > 0.0) || !isfinite(dk)) {
           dk = qnan<double>();
-          *bad = 1;
+          badf = 1;
         }
-        piv[k] = dk;
-        const double inv = 1.0 / dk;
+        const double s = lane > k ? v[k] / dk : 0.0;
 #pragma unroll
-        for (int i = k + 1; i < MAXM; ++i) cb[i] = v[i] * inv;
-      }
-      __syncthreads();
-      if (own && (!isH || c > k)) {
-        const double rk = v[k];
-#pragma unroll
-        for (int i = k + 1; i < MAXM; ++i) v[i] = fma(-cb[i], rk, v[i]);
+        for (int i = k + 1; i < MAXM; ++i) v[i] = fma(-readlane(v[i], k), s, v[i]);
       }
     }
+    if (isH) {
+      double dc = v[0];
+#pragma unroll
+      for (int i = 1; i < MAXM; ++i)
+        if (i == lane) dc = v[i];
+      if (!(dc > 0.0) || !isfinite(dc)) dc = qnan<double>();
+      const double inv = 1.0 / dc, sc = sqrt(dc);
+      double* col = G + lane * ldg;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        if (i > lane) col[i] = v[i] * inv;
+      buf[lane] = 1.0 / sc;
+      if (chol) {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+          if (i < m) chol[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
+      }
+    }
+    if (badf && lane == 0) *bad = 1;
+  }
+  __syncthreads();
+  const int nvc = m + nr + (ident ? m : 0);
+  const bool own = c >= m && c < nvc;
+  const bool fromG = c < m + nr;
+  const int q = c - m - nr;
+  double v[MAXM];
+  if (own) {
+    const double* src = G + (fromG ? c : 0) * ldg;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) v[i] = i < m ? (fromG ? src[i] : (i == q ? 1.0 : 0.0)) : 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+      if (k < m) {
+        const double rk = v[k];
+        const double* mk = G + k * ldg;
+#pragma unroll
+        for (int i = k + 1; i < MAXM; ++i) v[i] = fma(-mk[i], rk, v[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+      if (i < m) v[i] *= buf[i];
   }
   __syncthreads();
   if (own) {
-    if (isH) {
-      if (chol) {
-        const double sc = sqrt(piv[c]);
+    double* dst = fromG ? G + c * ldg : zi + q * ldzi;
 #pragma unroll
-        for (int i = 0; i < MAXM; ++i)
-          if (i < m) chol[i * m + c] = (i == c) ? sc : (i > c ? v[i] / sc : 0.0);
-      }
-    } else {
-      double* dst = fromG ? G + c * ldg : zi + q * ldzi;
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i) dst[i] = v[i] / sqrt(i < m ? piv[i] : 1.0);
-    }
+    for (int i = 0; i < MAXM; ++i) dst[i] = v[i];
   }
   __syncthreads();
 }

@@ -51,7 +51,7 @@ def streamed(n, m):
     kernels use widths of at least 16)."""
     w = pad_rows(max(m, 9) if n >= 32 else m)
     W = m + 2 * n + 1
-    dbl = n * n + n + n * (m + n + 1) + n * W + (w + 1) * W + 3 * w + n * n + 2 * n
+    dbl = n * (n | 1) + n + n * (m + n + 1) + n * W + (w + 1) * W + 3 * w + n * n + 2 * n
     return dbl * 8 + 64 > 160 * 1024
 
 

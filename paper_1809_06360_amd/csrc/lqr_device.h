@@ -33,11 +33,13 @@ namespace lqr {
 
 // LDS of one sweep. G (input Hessian and right-hand sides) is column-major
 // with leading dimension mp = MW + 1 (MW the kernel's register width, >= m):
-// element (i, j) at G[j * mp + i].
+// element (i, j) at G[j * mp + i]. P is row-major with the odd leading
+// dimension ldp = p_ld(n), so that the 16 rows a matrix-core operand fetch
+// reads fall in distinct LDS banks.
 struct SweepLds {
   double *P, *p, *X, *Y, *G, *E, *Psi, *psi, *gc;
   int* bad;
-  int WX, W, mp;
+  int WX, W, mp, ldp;
 };
 
 LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual, int mw) {
@@ -45,7 +47,8 @@ LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual, int mw) {
   s.WX = m + n + 1;
   s.W = sweep_w(n, m, dual);
   double* q = smem;
-  s.P = q; q += n * n;
+  s.ldp = p_ld(n);
+  s.P = q; q += n * s.ldp;
   s.p = q; q += n;
   s.X = q; q += n * s.WX;
   s.Y = q; q += n * s.W;
@@ -132,7 +135,7 @@ LQR_DEV void stage_products(const InstDesc& d, const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX, W = s.W;
   double* Y = s.Y;
   const double* p = s.p;
-  pgemm_sub<E, false, false, false, false>(n, WX, n, s.P, n, s.X, WX, 0, s.P, n, s.X, WX,
+  pgemm_sub<E, false, false, false, false>(n, WX, n, s.P, s.ldp, s.X, WX, 0, s.P, s.ldp, s.X, WX,
                                         [=](int i, int j, double v) {
                                           if (j == m + n) v += p[i];
                                           Y[i * W + j] = v;
@@ -170,13 +173,14 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
   const double* qt = d.q + (size_t)t * n;
   double* P = s.P;
   double* p = s.p;
+  const int ldp = s.ldp;
   pgemm_sub<E, true, false, false, true>(n, n + 1, n, s.X + m, s.WX, s.Y + m, W, m, s.G + m * s.mp, s.mp, s.G + m * s.mp, s.mp,
       [=](int i, int j, double v) {
         if (j < n) {
           if (i >= j) {
             v += 0.5 * (Qt[i * n + j] + Qt[j * n + i]);
-            P[i * n + j] = v;
-            P[j * n + i] = v;
+            P[i * ldp + j] = v;
+            P[j * ldp + i] = v;
             if (Pg) {
               Pg[i * n + j] = v;
               Pg[j * n + i] = v;
@@ -204,12 +208,13 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
                         const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX;
   if (threadIdx.x == 0) *s.bad = 0;
-  load_block(s.P, n, Pend, n, n, n);
+  load_block(s.P, s.ldp, Pend, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) s.p[i] = pend[i];
   int fail = 0;
   double* dead = reinterpret_cast<double*>(s.bad) + 1;
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
+    __builtin_amdgcn_sched_barrier(0);  // keep the warming loads behind the staging waits
     const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     stage_products<MM, E>(d, s);
@@ -255,7 +260,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   const int n = d.n, m = d.m, W = s.W, WX = s.WX;
   double* Gam = s.Y + WX;  // columns [WX, WX+n) of Y
   if (threadIdx.x == 0) *s.bad = 0;
-  fill_block(s.P, n, n, n, 0.0, 0.0);
+  fill_block(s.P, s.ldp, n, n, 0.0, 0.0);
   fill_block(s.Psi, n, n, n, 0.0, 0.0);
   fill_block(Gam, W, n, n, 0.0, 1.0);
   for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -266,6 +271,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   double* dead = reinterpret_cast<double*>(s.bad) + 1;
   for (int t = t1 - 1; t >= t0; --t) {
     load_stage(d, t, s);
+    __builtin_amdgcn_sched_barrier(0);  // keep the warming loads behind the staging waits
     const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     stage_products<MM, E>(d, s);
@@ -313,7 +319,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   }
   __syncthreads();
   const int nn = n * n;
-  store_block(out, n, s.P, n, n, n);
+  store_block(out, n, s.P, s.ldp, n, n);
   store_block(out + nn, n, Gam, W, n, n);
   store_block(out + 2 * nn, n, s.Psi, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -334,8 +340,9 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
                           double* smem) {
   const int n = d.n, m = d.m, nn = n * n;
   const int WX = m + 1, WY = m + n + 1, mp = MM + 1;
-  double* P = smem;
-  double* p = P + nn;
+  const int ldp = p_ld(n);
+  double* P = smem;              // n x n, leading dimension ldp
+  double* p = P + n * ldp;
   double* X = p + n;             // n x (m+1): [B | c]
   double* Y = X + n * WX;        // n x (m+n+1): [PB | PA | Pc+p]
   double* G = Y + n * WY;        // mp x (m+2n+1) column-major
@@ -347,7 +354,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
   double* Gam = out + nn;
   double* Gn = gtmp;
   if (threadIdx.x == 0) *bad = 0;
-  fill_block(P, n, n, n, 0.0, 0.0);
+  fill_block(P, ldp, n, n, 0.0, 0.0);
   fill_block(Psi, n, n, n, 0.0, 0.0);
   fill_block(Gam, n, n, n, 0.0, 1.0);
   for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -363,15 +370,16 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     const double* rt = d.r + (size_t)t * m;
     load_block(X, WX, d.B + (size_t)t * n * m, m, n, m);
     for (int i = threadIdx.x; i < n; i += kThreads) X[i * WX + m] = ct[i];
+    __builtin_amdgcn_sched_barrier(0);  // keep the warming loads behind the staging waits
     const Touch next = touch_stage(d, t > t0 ? t - 1 : t);
     __syncthreads();
     // Y = P [B | A | c] + [0 | 0 | p]
-    pgemm_sub<E, false, false, false, false>(n, m + 1, n, P, n, X, WX, 0, P, n, X, WX,
+    pgemm_sub<E, false, false, false, false>(n, m + 1, n, P, ldp, X, WX, 0, P, ldp, X, WX,
         [=](int i, int j, double v) {
           if (j < m) Y[i * WY + j] = v;
           else Y[i * WY + m + n] = v + p[i];
         });
-    pgemm_sub<E, false, false, false, false>(n, n, n, P, n, At, n, 0, P, n, At, n,
+    pgemm_sub<E, false, false, false, false>(n, n, n, P, ldp, At, n, 0, P, ldp, At, n,
         [=](int i, int j, double v) { Y[i * WY + m + j] = v; });
     // gc = Gam' c (Gam of stage t+1)
     for (int i = threadIdx.x; i < n; i += kThreads) gc[i] = col_dot(Gam, n, X + m, WX, i, n);
@@ -398,8 +406,8 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
             if (j < n) {
               if (i >= j) {
                 v += 0.5 * (Qt[i * n + j] + Qt[j * n + i]);
-                P[i * n + j] = v;
-                P[j * n + i] = v;
+                P[i * ldp + j] = v;
+                P[j * ldp + i] = v;
               }
             } else {
               p[i] = v + qt[i];
@@ -432,7 +440,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     Gn = tmp;
   }
   __syncthreads();
-  store_block(out, n, P, n, n, n);
+  store_block(out, n, P, ldp, n, n);
   if (Gam != out + nn) store_block(out + nn, n, Gam, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) {
     out[3 * nn + i] = p[i];
@@ -576,7 +584,7 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
     write_terminal(d);
     fail = plain_sweep<MM, E>(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
     double* b = ws_bnd(d.ws, n, J, J - 1);
-    store_block(b, n, s.P, n, n, n);
+    store_block(b, n, s.P, s.ldp, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = s.p[i];
   }
   if (threadIdx.x == 0) d.fail[seg] = fail;

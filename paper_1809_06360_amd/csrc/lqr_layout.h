@@ -167,9 +167,13 @@ LQR_HD int pad_rows(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 24 ? 24 : m
 
 // `mw` is the register width of the kernel variant that runs the sweep
 // (pad_rows of the largest m in the launch).
+// Leading dimension of the value Hessian P in a sweep's LDS: n rounded up to
+// an odd count.
+LQR_HD int p_ld(int n) { return n | 1; }
+
 LQR_HD size_t sweep_lds(int n, int m, bool dual, int mw) {
   const size_t W = (size_t)sweep_w(n, m, dual), mp = (size_t)mw + 1;
-  size_t dbl = (size_t)n * n + n + (size_t)n * (m + n + 1) + (size_t)n * W + mp * W +
+  size_t dbl = (size_t)n * p_ld(n) + n + (size_t)n * (m + n + 1) + (size_t)n * W + mp * W +
                3 * (size_t)mw;
   if (dual) dbl += (size_t)n * n + 2 * (size_t)n;
   return dbl * 8 + 64;
@@ -184,7 +188,7 @@ constexpr size_t kLdsSweepMax = 160 * 1024;
 // (Gamma and Psi stay in global memory).
 LQR_HD size_t sweep_lds_gs(int n, int m, int mw) {
   const size_t W = (size_t)m + 2 * (size_t)n + 1, mp = (size_t)mw + 1;
-  const size_t dbl = (size_t)n * n + n + (size_t)n * (m + 1) + (size_t)n * (m + n + 1) + mp * W +
+  const size_t dbl = (size_t)n * p_ld(n) + n + (size_t)n * (m + 1) + (size_t)n * (m + n + 1) + mp * W +
                      3 * (size_t)mw + 2 * (size_t)n;
   return dbl * 8 + 64;
 }

@@ -122,12 +122,33 @@ LQR_DEV void gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb,
 // ---------------------------------------------------------------------------
 // Copies between global memory and LDS (row-major, rows x cols).
 // ---------------------------------------------------------------------------
+// load_block issues up to U loads per thread before it stores any of them, so
+// a block costs about one memory round trip per U * kThreads elements. A
+// thread's elements are kThreads apart; (i, j) advance without divisions.
 template <typename T>
 LQR_DEV void load_block(T* dst, int ldd, const T* __restrict__ src, int lds, int rows, int cols) {
+  constexpr int U = 8;
   const int total = rows * cols;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    const int i = e / cols, j = e - i * cols;
-    dst[i * ldd + j] = src[i * lds + j];
+  const int di = kThreads / cols, dj = kThreads - di * cols;
+  int i = threadIdx.x / cols, j = threadIdx.x - i * cols;
+  for (int e0 = threadIdx.x; e0 < total; e0 += U * kThreads) {
+    T v[U];
+    int ii[U], jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ii[u] = i;
+      jj[u] = j;
+      v[u] = e0 + u * kThreads < total ? src[i * lds + j] : T(0);
+      i += di;
+      j += dj;
+      if (j >= cols) {
+        j -= cols;
+        ++i;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * kThreads < total) dst[ii[u] * ldd + jj[u]] = v[u];
   }
 }
 
@@ -222,6 +243,12 @@ LQR_HD int pad_ld(int m) { return pad_rows(m) + 1; }
 //  2. Every right-hand side (one thread per column) runs the unit-lower
 //     forward substitution with those multipliers and scales row i by
 //     1/sqrt(d_i).
+// When MAXM <= 32 and the right-hand sides fit in the waves' spare lanes
+// (kWaves (64 - m) of them), every wave instead factors H redundantly in
+// lanes [0, m) and carries its share of the right-hand sides in lanes
+// [m, 64): a right-hand side y takes the same round-k update as H's columns,
+// y_i -= H(i, k) (y_k / d_k), so step 2 and its barriers disappear; the
+// waves compute identical factors.
 // The loops are unrolled for m <= MAXM so every register index is fixed.
 //
 // On return (ends with a barrier):
@@ -241,6 +268,62 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
   const int c = threadIdx.x;
   const int lane = c & 63;
   const int wave = __builtin_amdgcn_readfirstlane(c >> 6);
+  if constexpr (MAXM <= 32) {
+    const int nrhs = nr + (ident ? m : 0), per = 64 - m;
+    if (kWaves * per >= nrhs) {
+      const bool isH = lane < m;
+      const int r = wave * per + lane - m;  // right-hand side of this lane
+      const bool isR = !isH && r < nrhs;
+      const bool fromG = isR && r < nr;
+      const int q = r - nr;                 // identity column
+      const double* src = G + (isH ? lane : fromG ? m + r : 0) * ldg;
+      double v[MAXM];
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        v[i] = i < m ? ((isH || fromG) ? src[i] : ((isR && i == q) ? 1.0 : 0.0)) : 0.0;
+      __syncthreads();  // every wave has read H before any result overwrites it
+      int badf = 0;
+#pragma unroll
+      for (int k = 0; k < MAXM; ++k) {
+        if (k < m) {
+          double dk = readlane(v[k], k);
+          if (!(dk > 0.0) || !isfinite(dk)) {
+            dk = qnan<double>();
+            badf = 1;
+          }
+          const double s = (isR || lane > k) ? v[k] / dk : 0.0;
+#pragma unroll
+          for (int i = k + 1; i < MAXM; ++i) v[i] = fma(-readlane(v[i], k), s, v[i]);
+        }
+      }
+      // lane c < m: pivot d_c, scale 1/sqrt(d_c); right-hand sides: row i times 1/sqrt(d_i)
+      double dc = v[0];
+#pragma unroll
+      for (int i = 1; i < MAXM; ++i)
+        if (i == lane) dc = v[i];
+      if (!(dc > 0.0) || !isfinite(dc)) dc = qnan<double>();
+      const double sc = sqrt(dc), rs = 1.0 / sc;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        if (i < m) {
+          const double ri = readlane(rs, i);
+          if (isR) v[i] *= ri;
+        }
+      if (wave == 0 && isH && chol) {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+          if (i < m) chol[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
+      }
+      if (isR) {
+        double* dst = fromG ? G + (m + r) * ldg : zi + q * ldzi;
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) dst[i] = v[i];
+      }
+      if (badf && wave == 0 && lane == 0) *bad = 1;
+      __syncthreads();
+      return;
+    }
+  }
   if (wave == 0) {
     // rows m..MAXM-1 and lanes m..63 are zero padding: they stay zero
     double v[MAXM];

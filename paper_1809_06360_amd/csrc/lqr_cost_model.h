@@ -12,11 +12,11 @@
 namespace lqr {
 namespace cost {
 
-constexpr double kDual[2][4] = {{5.29604, 1.07675, 0.455264, 0}, {0, 0.642568, 0.1632, 1.87494}};
-constexpr double kDualStreamed[2][4] = {{0, 0, 0, 0}, {21.2248, 0.855609, 0, 1.06303}};
-constexpr double kPlain[2][4] = {{2.85994, 0.947504, 0.321034, 0.190963}, {0, 0.651159, 0, 2.36462}};
-constexpr double kRoll[2][4] = {{0.671614, 0.129015, 0.0993282, 0.201129}, {1.98254, 0.0762027, 0.0843853, 0.571415}};
-constexpr double kLink[2][4] = {{3.72888, 1.85297, 0, 6.82112}, {46.5308, 0, 0, 10.046}};
+constexpr double kDual[2][4] = {{9.7286, 0.730256, 0.429983, 0}, {0, 0.356084, 0.357421, 1.40153}};
+constexpr double kDualStreamed[2][4] = {{0, 0, 0, 0}, {18.2212, 0.670574, 0.102654, 0.879499}};
+constexpr double kPlain[2][4] = {{7.14759, 0.647563, 0.327282, 0}, {0, 0.56655, 0.11784, 1.3803}};
+constexpr double kRoll[2][4] = {{3.00464, 0.00973967, 0, 0}, {2.82051, 0, 0.00239331, 0.297841}};
+constexpr double kLink[2][4] = {{4.32689, 1.86254, 0, 6.81954}, {46.8948, 0, 0, 10.0985}};
 constexpr double kTask = 3.0;
 
 }  // namespace cost

@@ -121,6 +121,17 @@ def test_solve_rejects_null_pointers_and_small_workspace():
     assert e.value.status == L.ERR_WORKSPACE
 
 
+@pytest.mark.parametrize("n,m", [(65, 4), (8, 65), (65, 65)])
+def test_states_or_inputs_above_64_are_unsupported(n, m):
+    """The kernels hold up to 64 state and input rows in registers (the
+    elimination's columns, the forward simulation's rows); larger problems are
+    rejected at planning time, for every algorithm."""
+    for algo in ("parallel", "serial"):
+        with pytest.raises(L.LQRError) as e:
+            L.lqr_workspace_size(ctypes.byref(_prob(n, m, 16, 0)), 1, L.options(algo=algo))
+        assert e.value.status == L.ERR_UNSUPPORTED
+
+
 def test_oversized_problem_is_unsupported_not_crashing():
     with pytest.raises(L.LQRError) as e:
         L.lqr_workspace_size(ctypes.byref(_prob(200, 100, 16, 0)), 1, L.options())

@@ -100,6 +100,22 @@ def test_indefinite_input_hessian_is_reported(algo, J):
     assert int(got["info"][0]) == 7
 
 
+@pytest.mark.parametrize("n,m,T,J", [
+    (63, 32, 24, 3),   # parametric sweep with 2n + 1 = 127 right-hand sides: every wave factors H
+    (40, 48, 20, 2),   # m > 32: H factored by wave 0, substitution over LDS multipliers
+    (24, 8, 33, 1),    # plain sweep, right-hand sides [H_ux | h_u | I] in the spare lanes
+    (64, 32, 17, 1),   # 64 states, one segment: forward simulation with full 16-column blocks
+])
+def test_elimination_and_simulation_layouts_match_oracle(n, m, T, J):
+    """Cases on both sides of the lane budget of the Hessian elimination
+    (right-hand sides in the waves' spare lanes when m <= 32 and they fit) and
+    at the register-block limits of the forward simulation."""
+    prob = make_instance(26, 0, n, m, T)
+    got = _solve(prob, segments=J)
+    assert int(got["info"][0]) == 0
+    compare(got, oracle.solve(prob), label="%s" % ((n, m, T, J),))
+
+
 def test_outputs_not_requested_are_not_needed():
     import paper_1809_06360_amd as L
     prob = make_instance(24, 0, 10, 4, 40)

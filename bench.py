@@ -158,9 +158,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the batched instances and the segments of one instance would shard across GPUs, "
-              "see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
+              "(the batched instances and the segments of one instance would shard across GPUs)"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

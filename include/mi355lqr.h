@@ -40,6 +40,14 @@
  *    and runs asynchronously. Argument errors are returned synchronously;
  *    numerical failures are written asynchronously to the instance's `info`.
  *  - Calls that share a workspace must be ordered on one stream.
+ *  - Workspace regions (see lqr_workspace_layout): lqr_backward's plan, then
+ *    lqr_solve_batched's plan, then scratch. The plans of a problem set (the
+ *    same batch, n, m, T and segments per instance) sit in disjoint regions, so
+ *    one workspace can serve a batched forward call and lqr_backward on the same
+ *    problem set, eagerly or as captured graphs replayed in any order. A call
+ *    on a different problem set writes over those regions: it invalidates every
+ *    graph captured on the workspace, and a later capture there is rejected
+ *    until an uncaptured call has uploaded its plan again.
  */
 #ifndef MI355LQR_H
 #define MI355LQR_H
@@ -90,17 +98,25 @@ typedef enum {
 /* info codes (per instance, device int32, written asynchronously):
  *   0                         success
  *   t + 1  (1 <= info <= T)   the input Hessian R_t + B_t'P B_t (+ terms) of
- *                             stage t failed its Cholesky factorization (pivot
- *                             not positive or not finite); when several stages
- *                             fail, the largest such t is reported. The
- *                             instance's outputs are then NaN from that stage on.
+ *                             stage t is not positive definite (a finite pivot
+ *                             of its Cholesky factorization was not positive);
+ *                             when several stages fail, the largest such t is
+ *                             reported. The instance's outputs are then NaN
+ *                             from that stage on.
  *   LQR_INFO_COUPLING + j     the linking system at segment boundary j had a
  *                             zero or non-finite pivot.
  *   LQR_INFO_QUEUE            internal error of the persistent batched launch:
  *                             a task waited about ten seconds for a dependency
- *                             and gave up (outputs invalid).                   */
+ *                             and gave up (outputs invalid).
+ *   LQR_INFO_NONFINITE (< 0)  a non-finite value (NaN or infinity, normally from
+ *                             non-finite input data) reached a pivot of an input
+ *                             Hessian's factorization, a value gradient p_t, a
+ *                             state, an input or a costate; the outputs are not
+ *                             valid. Reported only when no positive code applies
+ *                             (lqr_backward does not report it).               */
 #define LQR_INFO_COUPLING 0x40000000
 #define LQR_INFO_QUEUE 0x20000000
+#define LQR_INFO_NONFINITE (-1)
 
 /* One LQR instance. */
 typedef struct {
@@ -217,6 +233,19 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t *probs, int32_t batch,
 lqr_status_t lqr_backward(const lqr_problem_t *probs, int32_t batch,
                           const lqr_grad_t *grads, const lqr_options_t *opts,
                           void *ws, size_t ws_bytes, void *stream);
+
+/* Byte regions of the workspace of these problems (HOST array of `batch`
+ * descriptors; only n, m, T and segments are read) under these options:
+ * out[0], out[1]  offset and size of the region holding lqr_backward's plan,
+ * out[2], out[3]  offset and size of the region holding lqr_solve_batched's plan,
+ * out[4]          offset of the scratch region (everything after it may be
+ *                 overwritten by any call),
+ * out[5]          bytes of lqr_backward's plan, out[6] bytes of
+ *                 lqr_solve_batched's plan (each at most its region's size),
+ * out[7]          lqr_workspace_size of the same arguments.
+ * Host only; `out` is a HOST array of 8 entries. */
+lqr_status_t lqr_workspace_layout(const lqr_problem_t *probs, int32_t batch,
+                                  const lqr_options_t *opts, size_t *out);
 
 /* Static description of a status code. */
 const char *lqr_status_string(lqr_status_t status);

@@ -17,11 +17,11 @@ import os
 
 __all__ = [
     "LIB_PATH", "library", "LqrProblem", "LqrOptions", "LqrGrad",
-    "lqr_workspace_size", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase", "lqr_solve_batched",
-    "lqr_backward", "lqr_status_string",
+    "lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase",
+    "lqr_solve_batched", "lqr_backward", "lqr_status_string",
     "solve", "solve_batched", "plan_segments", "backward", "LQRError",
     "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
-    "INFO_COUPLING", "FLAG_PHASED",
+    "INFO_COUPLING", "INFO_QUEUE", "INFO_NONFINITE", "FLAG_PHASED",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi355lqr.so")
@@ -32,6 +32,7 @@ PREC_FP64, PREC_MIXED, PREC_FP32 = 0, 1, 2
 ALGO_PARALLEL, ALGO_SERIAL = 0, 1
 INFO_COUPLING = 0x40000000
 INFO_QUEUE = 0x20000000
+INFO_NONFINITE = -1
 FLAG_PHASED = 0x1
 
 _vp = ctypes.c_void_p
@@ -53,8 +54,8 @@ class LqrGrad(ctypes.Structure):
                                          "dR", "dr", "dS", "dx0")]
 
 
-EXPORTS = ("lqr_workspace_size", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase",
-           "lqr_solve_batched", "lqr_backward", "lqr_status_string")
+EXPORTS = ("lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve",
+           "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string")
 
 _lib = None
 
@@ -76,6 +77,9 @@ def library():
         P = ctypes.POINTER
         lib.lqr_workspace_size.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), P(ctypes.c_size_t)]
         lib.lqr_workspace_size.restype = ctypes.c_int
+        lib.lqr_workspace_layout.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions),
+                                             P(ctypes.c_size_t)]
+        lib.lqr_workspace_layout.restype = ctypes.c_int
         lib.lqr_plan_segments.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), P(ctypes.c_int32),
                                           P(ctypes.c_double)]
         lib.lqr_plan_segments.restype = ctypes.c_int
@@ -108,6 +112,18 @@ def lqr_workspace_size(probs, batch: int, opts: LqrOptions) -> int:
     if st != SUCCESS:
         raise LQRError(st, "lqr_workspace_size")
     return int(out.value)
+
+
+def lqr_workspace_layout(probs, batch: int, opts: LqrOptions) -> dict:
+    """Byte regions of the workspace (see the C header): the two plan regions,
+    the scratch offset, the plans' sizes and the total workspace size."""
+    out = (ctypes.c_size_t * 8)()
+    st = library().lqr_workspace_layout(probs, int(batch), ctypes.byref(opts), out)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_workspace_layout")
+    v = [int(x) for x in out]
+    return dict(adj_off=v[0], adj_cap=v[1], fwd_off=v[2], fwd_cap=v[3], scratch_off=v[4],
+                adj_plan=v[5], fwd_plan=v[6], total=v[7])
 
 
 def lqr_plan_segments(probs, batch: int, opts: LqrOptions):
@@ -336,7 +352,10 @@ def _lqr_function():
         (A [N,T,n,n], B [N,T,n,m], c [N,T,n], Q [N,T+1,n,n], q [N,T+1,n],
         R [N,T,m,m], r [N,T,m], x0 [N,n]); outputs x [N,T+1,n], u [N,T,m].
         Forward: one lqr_solve_batched call; backward: one lqr_backward call
-        (adjoint re-solve on the KKT-transposed right-hand side)."""
+        (adjoint re-solve on the KKT-transposed right-hand side). Backward
+        raises LQRError if the forward solve reported a non-zero info word for
+        any instance (an indefinite stage, a linking failure or a non-finite
+        value): the gradients are not defined there."""
 
         @staticmethod
         def forward(ctx, A, B, c, Q, q, R, r, x0):
@@ -359,6 +378,12 @@ def _lqr_function():
             ts = ctx.saved_tensors
             big = ctx.big
             N = ts[0].shape[0]
+            bad = big["info"].ne(0).any(dim=1).nonzero().flatten().tolist()
+            if bad:
+                codes = big["info"][bad, 0].tolist()
+                raise LQRError(ERR_NOT_PD if all(c > 0 for c in codes) else ERR_NONFINITE,
+                               "LQRFunction.backward (forward solve info %s for instances %s)"
+                               % (codes[:8], bad[:8]))
             if gx is None:
                 gx = torch.zeros_like(big["x"])
             if gu is None:

@@ -33,7 +33,18 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    """Every translation unit, the slowest to compile first (the sweep and
+    persistent kernel variants), so that a parallel build ends sooner."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    heavy = ("k_sweep_phase1", "k_persistent_w", "k_sweep_phase3", "k_sweep_serial")
+
+    def rank(path):
+        name = os.path.basename(path)
+        for i, h in enumerate(heavy):
+            if name.startswith(h):
+                return i
+        return len(heavy)
+    return sorted(srcs, key=lambda p: (rank(p), p))
 
 
 def _compile(src, obj, verbose):

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64) void k_link_forward(InstDesc d) {
   }
   if (lane == 0) {
     int f = 0;
-    for (int j = 0; j < J; ++j) f = max(f, d.fail[j]);
+    for (int j = 0; j < J; ++j) f = combine_info(f, d.fail[j]);
     *d.info = f ? f : d.fail[J];
   }
 }
@@ -263,7 +263,6 @@ struct k_link_maps_ref {
 
 hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
   const int J = d.J, n = d.n;
-  const int eng = launch_engine(n, false);
   hipLaunchKernelGGL(k_link_init, dim3(J), dim3(kThreads), 0, stream, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -271,7 +270,7 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
   for (int dist = 1; dist < J; dist *= 2) {
     const double* in = ws_scan(d.ws, n, J, src);
     double* out = ws_scan(d.ws, n, J, 1 - src);
-    e = with_variant_fp64<k_link_combine_ref>(n, eng, [&](auto k) -> hipError_t {
+    e = with_link_variant<k_link_combine_ref>(n, [&](auto k) -> hipError_t {
       hipError_t e2 = ensure_dynamic_lds((const void*)k, lds);
       if (e2 != hipSuccess) return e2;
       hipLaunchKernelGGL(k, dim3(J), dim3(kThreads), lds, stream, d, dist, in, out);
@@ -281,14 +280,14 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
     src = 1 - src;
   }
   const double* fin = ws_scan(d.ws, n, J, src);
-  e = with_variant_fp64<k_link_maps_ref>(n, eng, [&](auto k) -> hipError_t {
+  e = with_link_variant<k_link_maps_ref>(n, [&](auto k) -> hipError_t {
     hipError_t e2 = ensure_dynamic_lds((const void*)k, lds);
     if (e2 != hipSuccess) return e2;
     hipLaunchKernelGGL(k, dim3(J), dim3(kThreads), lds, stream, d, fin);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return with_variant_fp64<k_link_forward_ref>(n, 0, [&](auto k) -> hipError_t {
+  return with_link_variant<k_link_forward_ref>(n, [&](auto k) -> hipError_t {
     hipLaunchKernelGGL(k, dim3(1), dim3(64), 64 * sizeof(double), stream, d);
     return hipGetLastError();
   });

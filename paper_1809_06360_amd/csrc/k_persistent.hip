@@ -5,7 +5,8 @@
 namespace lqr {
 
 #define LQR_DECL2(W) LQR_PERSISTENT_DECL(W, 0) LQR_PERSISTENT_DECL(W, 1) LQR_PERSISTENT_DECL(W, 2)
-LQR_DECL2(8) LQR_DECL2(16) LQR_DECL2(24) LQR_DECL2(32) LQR_DECL2(48) LQR_DECL2(64)
+LQR_PERSISTENT_DECL(8, 0)
+LQR_DECL2(16) LQR_DECL2(24) LQR_DECL2(32) LQR_DECL2(48) LQR_DECL2(64)
 #undef LQR_DECL2
 
 // Zero the synchronisation words (a kernel, not a memset, so that the launch
@@ -40,6 +41,10 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
   const int cus = device_cus();
   const unsigned li = (unsigned)lds_items;
   switch (pad_rows(max_m)) {
+    case 8:  // vector-ALU engine only (see with_variant)
+      if (eng != 0) return hipErrorInvalidValue;
+      return launch_persistent_variant<8, 0>(descs, tasks, ntasks, ninst, sync, li, lds, cus,
+                                             grid_out, stream);
 #define LQR_CASE(W)                                                                            \
   case W:                                                                                      \
     return eng == 2   ? launch_persistent_variant<W, 2>(descs, tasks, ntasks, ninst, sync, li, lds, \
@@ -48,7 +53,7 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
                                                         cus, grid_out, stream)                    \
                       : launch_persistent_variant<W, 0>(descs, tasks, ntasks, ninst, sync, li, lds, \
                                                         cus, grid_out, stream);
-    LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
+    LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
 #undef LQR_CASE
   }
   return hipErrorInvalidValue;

@@ -1,0 +1,8 @@
+// Persistent batched kernel, register width 64, FP64 matrix-core engine (see
+// k_persistent.h; one translation unit per variant so the library builds in
+// parallel).
+#include "k_persistent.h"
+
+namespace lqr {
+LQR_PERSISTENT_INST(64, 1)
+}  // namespace lqr

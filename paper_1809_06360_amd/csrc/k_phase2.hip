@@ -25,7 +25,8 @@ struct k_phase2_ref {
 
 hipError_t launch_k_phase2(const InstDesc& single, const InstDesc* descs, const WorkItem* items,
                    unsigned grid, int width, int eng, size_t lds, hipStream_t stream) {
-  return with_variant_fp64<k_phase2_ref>(width, eng, [&](auto k) -> hipError_t {
+  if (eng != launch_engine(width, false)) return hipErrorInvalidValue;
+  return with_link_variant<k_phase2_ref>(width, [&](auto k) -> hipError_t {
     hipError_t e = ensure_dynamic_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, stream, single, descs, items);

@@ -1,0 +1,7 @@
+// The phase-3 sweep kernels of the FP32 matrix-core engine, all register widths
+// (one translation unit per kernel and engine; see k_sweeps.h).
+#include "k_sweeps.h"
+
+namespace lqr {
+LQR_SWEEP_INST(kSweepPhase3, 2)
+}  // namespace lqr

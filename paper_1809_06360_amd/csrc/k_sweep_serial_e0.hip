@@ -1,0 +1,7 @@
+// The plain serial sweep kernels of the FP64 vector-ALU engine, all register widths
+// (one translation unit per kernel and engine; see k_sweeps.h).
+#include "k_sweeps.h"
+
+namespace lqr {
+LQR_SWEEP_INST(kSweepSerial, 0)
+}  // namespace lqr

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -62,15 +63,54 @@ struct InstPlan {
   size_t stage_off = 0;  // FP32 mode: FP64 staging of the instance's inputs and outputs
 };
 
-// Workspace layout of a call: descriptor table | phase-1/3 work items (phased
-// launches) | persistent task table | synchronisation words | per-instance
-// scratch. The first three (up to sync_off) form the uploaded plan.
+// Workspace regions of a problem set. They depend only on the instances'
+// n, m, T (not on the options), so lqr_solve_batched and lqr_backward on the
+// same problem set agree on them:
+//   [0, adj_cap)                   lqr_backward's uploaded plan
+//   [fwd_off, fwd_off + fwd_cap)   lqr_solve_batched's uploaded plan
+//   [scratch_off, ...)             per-call scratch (either call's)
+// Each plan region is sized for its largest possible table: every instance
+// split into T segments, and the FP32 conversion lists.
+struct Regions {
+  size_t adj_cap = 0, fwd_off = 0, fwd_cap = 0, scratch_off = 0;
+};
+
+// FP32 staging conversions per instance in a batched plan's table: up to 9
+// inputs in, 8 outputs out; in the adjoint's table: 10 in, 9 out.
+constexpr int kCvtPerInst = 17;
+constexpr int kAdjCvtPerInst = 19;
+
+int adj_blocks(int T) { return (T + 1 + kAdjStages - 1) / kAdjStages; }
+
+Regions regions_of(const lqr_problem_t* probs, int batch) {
+  size_t sum_t = 0, nb = 0;
+  for (int i = 0; i < batch; ++i) {
+    sum_t += (size_t)std::max(probs[i].T, 1);
+    nb += (size_t)adj_blocks(std::max(probs[i].T, 1));
+  }
+  Regions r;
+  r.adj_cap = align_up(sizeof(AdjDesc) * (size_t)batch) + align_up(sizeof(int2) * nb) +
+              align_up(sizeof(CvtItem) * (size_t)kAdjCvtPerInst * batch);
+  r.fwd_off = r.adj_cap;
+  r.fwd_cap = align_up(sizeof(InstDesc) * (size_t)batch) + align_up(sizeof(WorkItem) * sum_t) +
+              align_up(sizeof(TaskItem) * (2 * sum_t + (size_t)batch)) +
+              align_up(sizeof(CvtItem) * (size_t)kCvtPerInst * batch);
+  r.scratch_off = r.fwd_off + r.fwd_cap;
+  return r;
+}
+
+// Workspace layout of a forward call: in the batched-plan region, descriptor
+// table | phase-1/3 work items (phased launches) | persistent task table |
+// FP32 conversion list (together the uploaded plan, table_bytes from
+// table_off); in the scratch region, synchronisation words | FP32 staging |
+// per-instance scratch. Offsets are from the workspace base.
 struct BatchPlan {
   std::vector<InstPlan> inst;
   std::vector<TaskItem> tasks;  // persistent launch order (parallel algorithm)
   double est_us = 0.0;          // predicted makespan of the persistent launch
-  size_t items_off = 0, tasks_off = 0, cvt_off = 0, sync_off = 0;
-  size_t table_bytes = 0;       // = sync_off
+  Regions reg;
+  size_t table_off = 0, items_off = 0, tasks_off = 0, cvt_off = 0, sync_off = 0;
+  size_t table_bytes = 0;       // bytes of the uploaded plan
   size_t total_bytes = 0;
   int nitems = 0;
   int max_n = 1, max_m = 1;
@@ -81,9 +121,6 @@ bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL;
 bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
 bool is_mixed(const lqr_options_t* o) { return o && o->precision == LQR_PREC_MIXED; }
 bool is_f32(const lqr_options_t* o) { return o && o->precision == LQR_PREC_FP32; }
-// FP32 staging conversions per instance in a batched plan's table: up to 9
-// inputs in, 8 outputs out.
-constexpr int kCvtPerInst = 17;
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
@@ -173,12 +210,15 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
     plan->tasks = order_tasks(tin, J, mw, mf, planned_slots(plan->lds_persist), &plan->est_us);
   }
   plan->nitems = items;
-  plan->items_off = align_up(sizeof(InstDesc) * (size_t)batch);
+  plan->reg = regions_of(probs, batch);
+  plan->table_off = plan->reg.fwd_off;
+  plan->items_off = plan->table_off + align_up(sizeof(InstDesc) * (size_t)batch);
   plan->tasks_off = plan->items_off + align_up(sizeof(WorkItem) * (size_t)items);
   plan->cvt_off = plan->tasks_off + align_up(sizeof(TaskItem) * plan->tasks.size());
-  plan->sync_off = plan->cvt_off +
-                   (is_f32(opts) ? align_up(sizeof(CvtItem) * (size_t)kCvtPerInst * batch) : 0);
-  plan->table_bytes = plan->sync_off;
+  plan->table_bytes = plan->cvt_off - plan->table_off +
+                      (is_f32(opts) ? align_up(sizeof(CvtItem) * (size_t)kCvtPerInst * batch) : 0);
+  if (plan->table_bytes > plan->reg.fwd_cap) return LQR_ERR_INVALID_ARG;  // cannot happen: J <= T
+  plan->sync_off = plan->reg.scratch_off;
   size_t off = plan->sync_off + align_up(sizeof(int32_t) * sync_words(batch));
   if (is_f32(opts))
     for (int i = 0; i < batch; ++i) {
@@ -245,10 +285,13 @@ lqr_status_t check_device(const BatchPlan& plan) {
   return need <= lim ? LQR_SUCCESS : LQR_ERR_UNSUPPORTED;
 }
 
-// Adjoint layout: AdjDesc table, stage-block table, then per-instance scratch.
+// Adjoint layout: in the adjoint-plan region, AdjDesc table | stage-block
+// table | FP32 conversion list (the uploaded plan, table_bytes from offset 0);
+// in the scratch region, per-instance scratch and FP32 staging.
 struct AdjPlan {
   size_t table_bytes = 0, blocks_off = 0, cvt_off = 0, total_bytes = 0;
   int nblocks = 0;
+  Regions reg;
   std::vector<size_t> ws_off;
   std::vector<size_t> stage_off;  // FP32 mode staging per instance
   size_t lds = 0;
@@ -264,8 +307,6 @@ size_t adj_stage_doubles(int n, int m, int T) {
                      t * m * n + n;
   return in + out;
 }
-constexpr int kAdjCvtPerInst = 19;
-
 lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap, bool f32) {
   if (!probs || batch < 1) return LQR_ERR_INVALID_ARG;
   ap->ws_off.resize(batch);
@@ -275,14 +316,16 @@ lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap, b
     lqr_status_t st = check_dims(probs[i]);
     if (st != LQR_SUCCESS) return st;
     if (probs[i].m > 64) return LQR_ERR_UNSUPPORTED;
-    nb += (probs[i].T + 1 + kAdjStages - 1) / kAdjStages;
+    nb += adj_blocks(probs[i].T);
     ap->lds = std::max(ap->lds, adj_lds(probs[i].n, probs[i].m));
   }
   ap->nblocks = nb;
+  ap->reg = regions_of(probs, batch);
   ap->blocks_off = align_up(sizeof(AdjDesc) * (size_t)batch);
   ap->cvt_off = ap->blocks_off + align_up(sizeof(int2) * (size_t)nb);
   ap->table_bytes = ap->cvt_off + (f32 ? align_up(sizeof(CvtItem) * (size_t)kAdjCvtPerInst * batch) : 0);
-  size_t off = ap->table_bytes;
+  if (ap->table_bytes > ap->reg.adj_cap) return LQR_ERR_INVALID_ARG;  // cannot happen
+  size_t off = ap->reg.scratch_off;
   for (int i = 0; i < batch; ++i) {
     ap->ws_off[i] = off;
     off += align_up(adj_ws_doubles(probs[i].n, probs[i].m, probs[i].T) * sizeof(double));
@@ -368,12 +411,148 @@ InstDesc make_desc_f32(const lqr_problem_t& p, int J, char* ws_base, size_t ws_o
   return d;
 }
 
-// Host copies of uploaded batched plans, keyed by workspace address, so that
-// a call under stream capture can verify that the plan it needs is resident.
+// Host copies of the plans uploaded into each workspace (keyed by its
+// address), so that a call under stream capture can verify that the plan it
+// needs is resident. `layout` is the dims key of the problem set whose regions
+// hold them. A host buffer handed to hipMemcpyAsync stays alive until an
+// event recorded after the copy has completed (retired buffers are released
+// by later calls once their copies are done).
+struct Upload {
+  std::vector<char> bytes;
+  hipEvent_t done = nullptr;
+};
+struct WsPlans {
+  std::vector<int32_t> layout;
+  std::unique_ptr<Upload> fwd, adj;
+};
 std::mutex g_plan_mu;
-std::map<void*, std::vector<char>> g_plans;
+std::map<void*, WsPlans> g_plans;
+std::vector<std::unique_ptr<Upload>> g_retired;
+
+std::vector<int32_t> layout_key(const lqr_problem_t* probs, int batch) {
+  std::vector<int32_t> key;
+  key.reserve(1 + 3 * (size_t)batch);
+  key.push_back(batch);
+  for (int i = 0; i < batch; ++i) {
+    key.push_back(probs[i].n);
+    key.push_back(probs[i].m);
+    key.push_back(probs[i].T);
+  }
+  return key;
+}
+
+// Caller holds g_plan_mu.
+void retire(std::unique_ptr<Upload>& u) {
+  if (u) g_retired.push_back(std::move(u));
+}
+
+void release_finished_uploads() {
+  for (size_t i = 0; i < g_retired.size();) {
+    Upload* u = g_retired[i].get();
+    if (!u->done || hipEventQuery(u->done) != hipErrorNotReady) {
+      if (u->done) (void)hipEventDestroy(u->done);
+      g_retired[i] = std::move(g_retired.back());
+      g_retired.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+// A call that only writes scratch in the layout of `key` (lqr_solve,
+// lqr_solve_phase): plans of another layout in this workspace may be
+// overwritten, so they are forgotten (a later capture needs a fresh upload).
+void forget_other_layouts(void* ws, const std::vector<int32_t>& key) {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  auto it = g_plans.find(ws);
+  if (it == g_plans.end() || it->second.layout == key) return;
+  retire(it->second.fwd);
+  retire(it->second.adj);
+  g_plans.erase(it);
+}
+
+// Upload `table` to ws + off (uncaptured stream), or check that exactly this
+// plan is resident (captured stream). `adj` selects the plan slot.
+lqr_status_t place_plan(void* ws, size_t off, bool adj, const std::vector<int32_t>& key,
+                        std::vector<char>&& table, hipStream_t s) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  if (cap != hipStreamCaptureStatusNone) {
+    auto it = g_plans.find(ws);
+    if (it == g_plans.end() || it->second.layout != key) return LQR_ERR_INVALID_ARG;
+    const std::unique_ptr<Upload>& u = adj ? it->second.adj : it->second.fwd;
+    return (u && u->bytes == table) ? LQR_SUCCESS : LQR_ERR_INVALID_ARG;
+  }
+  release_finished_uploads();
+  WsPlans& w = g_plans[ws];
+  if (w.layout != key) {  // another problem set's regions: its plans are overwritten
+    retire(w.fwd);
+    retire(w.adj);
+    w.layout = key;
+  }
+  std::unique_ptr<Upload>& slot = adj ? w.adj : w.fwd;
+  retire(slot);
+  std::unique_ptr<Upload> u(new Upload);
+  u->bytes = std::move(table);
+  if (hipMemcpyAsync(static_cast<char*>(ws) + off, u->bytes.data(), u->bytes.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return LQR_ERR_HIP;
+  if (hipEventCreateWithFlags(&u->done, hipEventDisableTiming) != hipSuccess) {
+    u->done = nullptr;
+    g_retired.push_back(std::move(u));  // kept until the process ends
+    return LQR_ERR_HIP;
+  }
+  if (hipEventRecord(u->done, s) != hipSuccess) {
+    (void)hipEventDestroy(u->done);
+    u->done = nullptr;
+    g_retired.push_back(std::move(u));
+    return LQR_ERR_HIP;
+  }
+  slot = std::move(u);
+  return LQR_SUCCESS;
+}
 
 }  // namespace
+
+// lqr_solve on a caller-given device buffer (the workspace, or the library's
+// own scratch array for lqr_solve_noalloc). Allocates no device memory.
+lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, void* ws,
+                          size_t ws_bytes, void* stream) {
+  BatchPlan plan;
+  lqr_status_t st = make_plan(prob, 1, opts, &plan);
+  if (st != LQR_SUCCESS) return st;
+  if ((st = check_pointers(*prob)) != LQR_SUCCESS) return st;
+  if ((st = check_device(plan)) != LQR_SUCCESS) return st;
+  if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+  forget_other_layouts(ws, layout_key(prob, 1));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int eng = launch_engine(plan.max_n, is_mixed(opts) || is_f32(opts));
+  InstDesc d;
+  CvtList cin{}, cout{};
+  if (is_f32(opts)) {
+    d = make_desc_f32(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off,
+                      plan.inst[0].stage_off, cin.it, &cin.n, cout.it, &cout.n);
+  } else {
+    d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
+  }
+  hipError_t e = launch_convert_list(cin, s);
+  if (e == hipSuccess)
+    e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
+                        : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+  if (e == hipSuccess) e = launch_convert_list(cout, s);
+  return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+}
+
+// Bytes lqr_solve needs for this problem (the plan's total), or an error.
+lqr_status_t solve_bytes(const lqr_problem_t* prob, const lqr_options_t* opts, size_t* bytes) {
+  BatchPlan plan;
+  lqr_status_t st = make_plan(prob, 1, opts, &plan);
+  if (st == LQR_SUCCESS) *bytes = plan.total_bytes;
+  return st;
+}
+
 }  // namespace lqr
 
 using namespace lqr;
@@ -413,32 +592,33 @@ lqr_status_t lqr_workspace_size(const lqr_problem_t* probs, int32_t batch, const
   }
 }
 
+lqr_status_t lqr_workspace_layout(const lqr_problem_t* probs, int32_t batch,
+                                  const lqr_options_t* opts, size_t* out) {
+  try {
+    if (!out) return LQR_ERR_INVALID_ARG;
+    BatchPlan plan;
+    lqr_status_t st = make_plan(probs, batch, opts, &plan);
+    if (st != LQR_SUCCESS) return st;
+    AdjPlan ap;
+    const bool adj_ok = make_adj_plan(probs, batch, &ap, is_f32(opts)) == LQR_SUCCESS;
+    out[0] = 0;
+    out[1] = plan.reg.adj_cap;
+    out[2] = plan.reg.fwd_off;
+    out[3] = plan.reg.fwd_cap;
+    out[4] = plan.reg.scratch_off;
+    out[5] = adj_ok ? ap.table_bytes : 0;
+    out[6] = plan.table_bytes;
+    out[7] = adj_ok ? std::max(plan.total_bytes, ap.total_bytes) : plan.total_bytes;
+    return LQR_SUCCESS;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
 lqr_status_t lqr_solve(const lqr_problem_t* prob, const lqr_options_t* opts, void* ws,
                        size_t ws_bytes, void* stream) {
   try {
-    BatchPlan plan;
-    lqr_status_t st = make_plan(prob, 1, opts, &plan);
-    if (st != LQR_SUCCESS) return st;
-    if ((st = check_pointers(*prob)) != LQR_SUCCESS) return st;
-    if ((st = check_device(plan)) != LQR_SUCCESS) return st;
-    if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
-    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int eng = launch_engine(plan.max_n, is_mixed(opts) || is_f32(opts));
-    InstDesc d;
-    CvtList cin{}, cout{};
-    if (is_f32(opts)) {
-      d = make_desc_f32(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off,
-                        plan.inst[0].stage_off, cin.it, &cin.n, cout.it, &cout.n);
-    } else {
-      d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
-    }
-    hipError_t e = launch_convert_list(cin, s);
-    if (e == hipSuccess)
-      e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
-                          : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
-    if (e == hipSuccess) e = launch_convert_list(cout, s);
-    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+    return lqr::solve_single(prob, opts, ws, ws_bytes, stream);
   } catch (...) {
     return LQR_ERR_INVALID_ARG;
   }
@@ -456,6 +636,7 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
     if ((st = check_device(plan)) != LQR_SUCCESS) return st;
     if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+    forget_other_layouts(ws, layout_key(prob, 1));
     const InstDesc d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
@@ -505,10 +686,10 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     // phased launches, longest segments first; the persistent task order.
     std::vector<char> table(plan.table_bytes, 0);
     InstDesc* descs = reinterpret_cast<InstDesc*>(table.data());
-    WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + plan.items_off);
-    TaskItem* tasks = reinterpret_cast<TaskItem*>(table.data() + plan.tasks_off);
+    WorkItem* items = reinterpret_cast<WorkItem*>(table.data() + (plan.items_off - plan.table_off));
+    TaskItem* tasks = reinterpret_cast<TaskItem*>(table.data() + (plan.tasks_off - plan.table_off));
     const bool f32 = is_f32(opts);
-    CvtItem* cvt = reinterpret_cast<CvtItem*>(table.data() + plan.cvt_off);
+    CvtItem* cvt = reinterpret_cast<CvtItem*>(table.data() + (plan.cvt_off - plan.table_off));
     std::vector<CvtItem> couts;
     int ncin = 0;
     std::vector<std::pair<double, WorkItem>> order;
@@ -542,21 +723,9 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     const int ncout = (int)couts.size();
 
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
-    {
-      std::lock_guard<std::mutex> lock(g_plan_mu);
-      if (cap != hipStreamCaptureStatusNone) {
-        auto it = g_plans.find(ws);
-        if (it == g_plans.end() || it->second != table) return LQR_ERR_INVALID_ARG;
-      } else {
-        std::vector<char>& keep = g_plans[ws];
-        keep = table;
-        if (hipMemcpyAsync(ws, keep.data(), keep.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-          return LQR_ERR_HIP;
-      }
-    }
-    const InstDesc* ddesc = reinterpret_cast<const InstDesc*>(base);
+    st = place_plan(ws, plan.table_off, false, layout_key(probs, batch), std::move(table), s);
+    if (st != LQR_SUCCESS) return st;
+    const InstDesc* ddesc = reinterpret_cast<const InstDesc*>(base + plan.table_off);
     const WorkItem* ditems = reinterpret_cast<const WorkItem*>(base + plan.items_off);
     const TaskItem* dtasks = reinterpret_cast<const TaskItem*>(base + plan.tasks_off);
     int32_t* dsync = reinterpret_cast<int32_t*>(base + plan.sync_off);
@@ -676,20 +845,8 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
     std::copy(couts.begin(), couts.end(), cvt + ncin);
     const int ncout = (int)couts.size();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return LQR_ERR_HIP;
-    {
-      std::lock_guard<std::mutex> lock(g_plan_mu);
-      if (cap != hipStreamCaptureStatusNone) {
-        auto it = g_plans.find(ws);
-        if (it == g_plans.end() || it->second != table) return LQR_ERR_INVALID_ARG;
-      } else {
-        std::vector<char>& keep = g_plans[ws];
-        keep = table;
-        if (hipMemcpyAsync(ws, keep.data(), keep.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-          return LQR_ERR_HIP;
-      }
-    }
+    st = place_plan(ws, 0, true, layout_key(probs, batch), std::move(table), s);
+    if (st != LQR_SUCCESS) return st;
     const CvtItem* dcvt = reinterpret_cast<const CvtItem*>(base + ap.cvt_off);
     hipError_t e = launch_convert(dcvt, ncin, s);
     if (e == hipSuccess)

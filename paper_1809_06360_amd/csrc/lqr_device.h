@@ -65,6 +65,31 @@ LQR_DEV SweepLds carve_sweep(double* smem, int n, int m, bool dual, int mw) {
   return s;
 }
 
+// Status codes of a sweep (the per-instance info word's encoding): t + 1 for
+// the largest stage t whose input Hessian was not positive definite,
+// LQR_INFO_NONFINITE if a non-finite value reached a pivot (and no stage was
+// found indefinite first), else 0. `bad` is the elimination's flag of stage t
+// (1: indefinite, 2: non-finite pivot).
+LQR_DEV int note_pivot(int code, int bad, int t) {
+  if (bad == 1 && code <= 0) return t + 1;
+  if (bad == 2 && code == 0) return LQR_INFO_NONFINITE;
+  return code;
+}
+
+// Two status codes into one: a stage or linking failure (positive) outranks a
+// non-finite value (negative), which outranks success; among positive codes
+// the larger wins. Commutative and associative, so the result does not depend
+// on the order in which segments report.
+LQR_HD int combine_info(int a, int b) { return (a > 0 || b > 0) ? (a > b ? a : b) : (a < b ? a : b); }
+
+// Fold a status code into the instance's info word from concurrent segments.
+LQR_DEV void report_info(int32_t* info, int code) {
+  if (code > 0)
+    atomicMax(info, code);
+  else if (code < 0)
+    atomicCAS(info, 0, code);
+}
+
 // Cache warming for the next stage of a backward sweep: one double of every
 // 128-byte line of stage t's inputs (A, B, c, Q, q, R, r, S), up to
 // kTouch * kThreads lines, is loaded into registers. Issued right after a
@@ -190,6 +215,7 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
           v += qt[i];
           p[i] = v;
           if (pg) pg[i] = v;
+          if (!isfinite(v)) s.bad[1] = 1;  // non-finite value gradient
         }
       },
       SkipUpper{n});
@@ -201,13 +227,17 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
 // h_u = r + B'(Pc + p)):
 //   [K | k] = -L^{-T} Z,   P <- Q + A'PA - Z_ux'Z_ux,   p <- q + A'(Pc+p) - Z_ux'z_h.
 // Writes K_t, k_t and, when requested, chol_t, P_t, p_t for t in [t0, t1).
-// Leaves the value at t0 in LDS (s.P, s.p). Returns (largest failing stage)
-// + 1, or 0; uniform across the workgroup.
+// Leaves the value at t0 in LDS (s.P, s.p). Returns a status code (see
+// note_pivot; also LQR_INFO_NONFINITE for a non-finite value gradient),
+// uniform across the workgroup.
 template <int MM, int E>
 LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, const double* pend,
                         const SweepLds& s) {
   const int n = d.n, m = d.m, WX = s.WX;
-  if (threadIdx.x == 0) *s.bad = 0;
+  if (threadIdx.x == 0) {
+    s.bad[0] = 0;
+    s.bad[1] = 0;
+  }
   load_block(s.P, s.ldp, Pend, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) s.p[i] = pend[i];
   int fail = 0;
@@ -225,7 +255,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
     // into G, L^{-1} into G's first m columns (column q of L^{-1} in column q)
     ldl_columns<MM>(s.G, s.mp, m, n + 1, true, s.G, s.mp,
                     d.chol ? d.chol + (size_t)t * m * m : nullptr, s.E, s.bad);
-    if (!fail && *s.bad) fail = t + 1;
+    fail = note_pivot(fail, *s.bad, t);
     stage_value<MM, E>(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
                 d.p ? d.p + (size_t)t * n : nullptr);
     {  // [K | k] = -H^{-1}[H_ux | h_u] = -(L^{-1})' Z
@@ -243,7 +273,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
     sink(next, dead);
     __syncthreads();
   }
-  return fail;
+  return (fail == 0 && s.bad[1]) ? LQR_INFO_NONFINITE : fail;
 }
 
 // Parametric (dual-form) sweep of a middle segment [t0, t1): the cost-to-go
@@ -283,7 +313,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
     stage_hessian<MM, E>(d, t, s, W);
     __syncthreads();
     ldl_columns<MM>(s.G, s.mp, m, 2 * n + 1, false, nullptr, 0, nullptr, s.E, s.bad);
-    if (!fail && *s.bad) fail = t + 1;
+    fail = note_pivot(fail, *s.bad, t);
     stage_value<MM, E>(d, t, s, nullptr, nullptr);
     {  // [psi-part | Psi-part] = Z_W' [z_h | Z_W]
       double* Psi = s.Psi;
@@ -396,7 +426,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
         [=](int i, int j, double v) { G[(m + n + 1 + j) * mp + i] = v; });
     __syncthreads();
     ldl_columns<MM>(G, mp, m, 2 * n + 1, false, nullptr, 0, nullptr, Eb, bad);
-    if (!fail && *bad) fail = t + 1;
+    fail = note_pivot(fail, *bad, t);
     {  // [P | p] <- [Q | q] + A'[PA | Pc+p] - Z_ux'[Z_ux | z_h]
       const double* Qt = d.Q + (size_t)t * nn;
       const double* qt = d.q + (size_t)t * n;
@@ -472,14 +502,15 @@ LQR_DEV double row_block_dot(const double (&r)[16], double v, int c0, int cw, do
 // Forward simulation of stages [t0, t1) from x_{t0} = xs (global):
 // u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t; writes x_t, u_t
 // (and lam_t = P_t x_t + p_t when requested), plus x_T (lam_T) if last.
-// n, m <= 64. Every wave holds the state in registers (lane i: x_i, u_i).
+// Returns LQR_INFO_NONFINITE (uniformly) if any value it wrote is not finite,
+// else 0. n, m <= 64. Every wave holds the state in registers (lane i: x_i, u_i).
 // Each matrix-vector product is split by columns over the waves (wave w takes
 // a contiguous quarter of the columns, lane i row i); the partial sums meet in
 // LDS and every wave adds them up in the same order, so a stage costs two
 // barriers. The next stage's matrix rows are loaded into registers while the
 // current stage is computed, which keeps global-memory latency off the chain.
 // LDS: rollout_lds.
-LQR_DEV void rollout(const InstDesc& d, int t0, int t1, const double* xs, bool last, double* smem) {
+LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool last, double* smem) {
   const int n = d.n, m = d.m, T = d.T;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -508,6 +539,7 @@ LQR_DEV void rollout(const InstDesc& d, int t0, int t1, const double* xs, bool l
     bc = rn ? d.c[(size_t)t * n + lane] : 0.0;
   };
   double x = rn ? xs[lane] : 0.0, u = 0.0;
+  bool finite = true;  // every value this lane wrote so far
   if (t0 < t1) {
     if (want_lam) fetch_value(t0);
     fetch_gain(t0);
@@ -531,8 +563,12 @@ LQR_DEV void rollout(const InstDesc& d, int t0, int t1, const double* xs, bool l
       sl += part1[w * 128 + lane];
       su += part1[w * 128 + 64 + lane];
     }
-    if (want_lam && wave == 2 && rn) d.lam[(size_t)t * n + lane] = cp + sl;
+    if (want_lam && wave == 2 && rn) {
+      d.lam[(size_t)t * n + lane] = cp + sl;
+      finite = finite && isfinite(cp + sl);
+    }
     u = rm ? ck + su : 0.0;
+    finite = finite && isfinite(x) && isfinite(u);
     if (wave == 1 && rm) d.u[(size_t)t * m + lane] = u;
     // partial A x + B u
     part2[wave * 64 + lane] = row_block_dot(pB, u, m0, cm, row_block_dot(pA, x, n0, cn, 0.0));
@@ -546,16 +582,20 @@ LQR_DEV void rollout(const InstDesc& d, int t0, int t1, const double* xs, bool l
   }
   if (last) {
     if (wave == 0 && rn) d.x[(size_t)T * n + lane] = x;
+    finite = finite && isfinite(x);
     if (want_lam) {
       part1[wave * 128 + lane] = row_block_dot(pP, x, n0, cn, 0.0);
       __syncthreads();
       double sl = 0.0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) sl += part1[w * 128 + lane];
-      if (wave == 2 && rn) d.lam[(size_t)T * n + lane] = bp + sl;
+      if (wave == 2 && rn) {
+        d.lam[(size_t)T * n + lane] = bp + sl;
+        finite = finite && isfinite(bp + sl);
+      }
     }
   }
-  __syncthreads();
+  return __syncthreads_or(finite ? 0 : 1) ? LQR_INFO_NONFINITE : 0;
 }
 
 // Terminal value P_T = Q_T, p_T = q_T into the outputs (if requested).
@@ -613,8 +653,8 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
 
   if (threadIdx.x == 0) {
     int f = 0;
-    for (int j = 0; j < J; ++j) f = max(f, d.fail[j]);
-    flag[0] = f;  // stage failure from phase 1
+    for (int j = 0; j < J; ++j) f = combine_info(f, d.fail[j]);
+    flag[0] = f;  // stage failure (or non-finite value) from phase 1
     flag[1] = 0;  // linking failure
     flag[2] = 0;  // pivot flag of the current boundary
   }
@@ -706,9 +746,10 @@ LQR_DEV void phase3_item(const InstDesc& d, int seg, double* smem) {
     SweepLds s = carve_sweep(smem, n, m, false, MM);
     const double* b = ws_bnd(d.ws, n, J, seg + 1);
     const int fail = plain_sweep<MM, E>(d, t0, t1, b, b + n * n, s);
-    if (fail && threadIdx.x == 0) atomicMax(d.info, fail);
+    if (fail && threadIdx.x == 0) report_info(d.info, fail);
   }
-  rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
+  const int nf = rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
+  if (nf && threadIdx.x == 0) report_info(d.info, nf);
 }
 
 template <int MM, int E>
@@ -717,8 +758,8 @@ LQR_DEV void serial_item(const InstDesc& d, double* smem) {
   SweepLds s = carve_sweep(smem, n, m, false, MM);
   write_terminal(d);
   const int fail = plain_sweep<MM, E>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, s);
-  rollout(d, 0, T, d.x0, true, smem);
-  if (threadIdx.x == 0) *d.info = fail;
+  const int nf = rollout(d, 0, T, d.x0, true, smem);
+  if (threadIdx.x == 0) *d.info = combine_info(fail, nf);
 }
 
 

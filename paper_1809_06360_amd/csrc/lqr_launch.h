@@ -14,13 +14,19 @@ hipError_t ensure_dynamic_lds(const void* kernel, size_t lds);
 
 // Call f with the kernel instantiation K<pad_rows(width), eng> (eng: product
 // engine 0, 1 or 2, see pgemm_sub).
+// Width 8 exists only for the vector-ALU engine: the width-8 matrix-core
+// variants faulted the GPU (illegal address) on the streamed parametric sweep
+// and are not compiled; asking for one returns hipErrorInvalidValue
+// (kernel_width never does).
 template <template <int, int> class K, typename F>
 hipError_t with_variant(int width, int eng, F f) {
   switch (pad_rows(width)) {
+    case 8:
+      return eng == 0 ? f(K<8, 0>::fn()) : hipErrorInvalidValue;
 #define LQR_CASE(W) \
   case W:           \
     return eng == 2 ? f(K<W, 2>::fn()) : eng == 1 ? f(K<W, 1>::fn()) : f(K<W, 0>::fn());
-    LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
+    LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
 #undef LQR_CASE
   }
   return hipErrorInvalidValue;
@@ -30,11 +36,30 @@ hipError_t with_variant(int width, int eng, F f) {
 template <template <int, int> class K, typename F>
 hipError_t with_variant_fp64(int width, int eng, F f) {
   switch (pad_rows(width)) {
+    case 8:
+      return eng == 0 ? f(K<8, 0>::fn()) : hipErrorInvalidValue;
 #define LQR_CASE(W) \
   case W:           \
     return eng == 1 ? f(K<W, 1>::fn()) : f(K<W, 0>::fn());
-    LQR_CASE(8) LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
+    LQR_CASE(16) LQR_CASE(24) LQR_CASE(32) LQR_CASE(48) LQR_CASE(64)
 #undef LQR_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// As with_variant_fp64 for the linking-solve kernels, whose width and engine
+// both follow from the (largest) state dimension n: pad_rows(n) with the FP64
+// matrix-core engine from kMfmaMinN states on, the vector ALUs below. Only
+// those variants are compiled.
+template <template <int, int> class K, typename F>
+hipError_t with_link_variant(int n, F f) {
+  switch (pad_rows(n)) {
+    case 8: return f(K<8, 0>::fn());
+    case 16: return f(K<16, 0>::fn());
+    case 24: return f(K<24, 0>::fn());
+    case 32: return n >= kMfmaMinN ? f(K<32, 1>::fn()) : f(K<32, 0>::fn());
+    case 48: return f(K<48, 1>::fn());
+    case 64: return f(K<64, 1>::fn());
   }
   return hipErrorInvalidValue;
 }
@@ -45,7 +70,7 @@ inline int launch_engine(int max_n, bool mixed) { return mixed ? 2 : max_n >= kM
 
 // Register width (the m the kernel variant is picked for) of a launch: the
 // matrix-core engines run widths of at least 16 (their width-8 variants are not
-// used), the vector-ALU engine any width.
+// built, see with_variant), the vector-ALU engine any width.
 inline int kernel_width(int max_m, int eng) { return eng != 0 && max_m < 9 ? 9 : max_m; }
 
 // One launcher per kernel. `single` is used when descs == nullptr; otherwise

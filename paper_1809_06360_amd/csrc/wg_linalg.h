@@ -258,7 +258,8 @@ LQR_HD int pad_ld(int m) { return pad_rows(m) + 1; }
 //   if chol != nullptr: L written row-major to chol (m x m, zeros above);
 //   G's columns [0, m) hold the multipliers (unless zi overwrote them).
 // A pivot that is not positive or not finite is replaced by NaN (which then
-// propagates into every dependent result) and *bad is set to 1.
+// propagates into every dependent result) and *bad is set: to 1 if the first
+// such pivot was finite (H not positive definite), to 2 if it was not finite.
 // buf: MAXM doubles of LDS. Requires m <= 64, m + nr + (ident ? m : 0) <= 256
 // and a barrier between G's producer and this call.
 // ---------------------------------------------------------------------------
@@ -288,8 +289,8 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
         if (k < m) {
           double dk = readlane(v[k], k);
           if (!(dk > 0.0) || !isfinite(dk)) {
+            if (!badf) badf = isfinite(dk) ? 1 : 2;
             dk = qnan<double>();
-            badf = 1;
           }
           const double s = (isR || lane > k) ? v[k] / dk : 0.0;
 #pragma unroll
@@ -319,7 +320,7 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
 #pragma unroll
         for (int i = 0; i < MAXM; ++i) dst[i] = v[i];
       }
-      if (badf && wave == 0 && lane == 0) *bad = 1;
+      if (badf && wave == 0 && lane == 0) *bad = badf;
       __syncthreads();
       return;
     }
@@ -337,8 +338,8 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
       if (k < m) {
         double dk = readlane(v[k], k);
         if (!(dk > 0.0) || !isfinite(dk)) {
+          if (!badf) badf = isfinite(dk) ? 1 : 2;
           dk = qnan<double>();
-          badf = 1;
         }
         const double s = lane > k ? v[k] / dk : 0.0;
 #pragma unroll
@@ -363,7 +364,7 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
           if (i < m) chol[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
       }
     }
-    if (badf && lane == 0) *bad = 1;
+    if (badf && lane == 0) *bad = badf;
   }
   __syncthreads();
   const int nvc = m + nr + (ident ? m : 0);

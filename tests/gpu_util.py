@@ -34,3 +34,13 @@ def compare(got, ref, keys=OUTPUTS, tol=FP64_TOL, label=""):
     bad = {k: e for k, e in errs.items() if not (e <= tol)}
     assert not bad, "%s relative errors above %.1e: %s (all: %s)" % (label, tol, bad, errs)
     return errs
+
+
+def oracle_map(fn, items, workers=None):
+    """fn over items on a thread pool. The oracle's C calls release the GIL, so
+    the reference solutions of a whole batch take seconds on a multicore host."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    workers = workers or max(1, min(16, os.cpu_count() or 4))
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, items))

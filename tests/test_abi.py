@@ -212,3 +212,33 @@ def test_precision_modes():
         L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, WORKLOADS["mixed"].segments)), 1,
                              L.options("mixed"))
     assert e.value.status == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dims", [
+    [(4, 2, 64, 4)],
+    [(48, 24, 1024, 64)],
+    [(8, 4, 32, 0), (20, 7, 50, 5), (1, 1, 5, 0), (64, 32, 48, 6)],
+    [(16, 8, 128, 1)] * 37,
+])
+def test_workspace_plan_regions_are_disjoint(dims):
+    """lqr_backward's plan and lqr_solve_batched's plan of one problem set sit
+    in disjoint regions before the scratch region, for every option set, and
+    each plan fits its region; the regions depend on the problem set only, so
+    every call on it agrees on them."""
+    arr = (L.LqrProblem * len(dims))(*[L.LqrProblem(n, m, T, J) for (n, m, T, J) in dims])
+    seen = None
+    for prec in ("fp64", "mixed", "fp32"):
+        for algo in ("parallel", "serial"):
+            for phased in (False, True):
+                lay = L.lqr_workspace_layout(arr, len(dims), L.options(prec, algo, phased))
+                a0, a1 = lay["adj_off"], lay["adj_off"] + lay["adj_cap"]
+                f0, f1 = lay["fwd_off"], lay["fwd_off"] + lay["fwd_cap"]
+                assert a1 <= f0 or f1 <= a0, lay                 # disjoint plan regions
+                assert lay["scratch_off"] >= max(a1, f1), lay     # scratch after both
+                assert 0 < lay["adj_plan"] <= lay["adj_cap"], lay
+                assert 0 < lay["fwd_plan"] <= lay["fwd_cap"], lay
+                assert lay["total"] == L.lqr_workspace_size(arr, len(dims), L.options(prec, algo, phased))
+                assert lay["total"] > lay["scratch_off"]
+                regions = (a0, a1, f0, f1, lay["scratch_off"])
+                assert seen is None or regions == seen, (prec, algo, phased)
+                seen = regions

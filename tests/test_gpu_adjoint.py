@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import FP64_TOL, host, rel_err, to_device
+from gpu_util import FP64_TOL, host, oracle_map, rel_err, to_device
 from synthetic import WORKLOADS, make_instance
 
 pytestmark = pytest.mark.gpu
@@ -58,10 +58,10 @@ def test_backward_with_cross_term_matches_oracle():
         assert rel_err(got[0][k], ref[k]) <= FP64_TOL, k
 
 
-def test_lqr_function_on_differentiable_workload_sample():
+def test_lqr_function_on_differentiable_workload():
     """The 512-instance batch (n=16, m=8, T=128) through the autograd op in
-    one forward and one backward call; a fixed sample of instances is checked
-    against the oracle's gradient."""
+    one forward and one backward call; every gradient of every instance is
+    checked against the oracle's gradient."""
     import paper_1809_06360_amd as L
     w = WORKLOADS["diff"]
     probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
@@ -71,14 +71,14 @@ def test_lqr_function_on_differentiable_workload_sample():
     loss = (x * x).sum() + (u * u).sum()
     loss.backward()
     torch.cuda.synchronize()
-    rng = np.random.default_rng(11)
-    for i in sorted(rng.choice(w.batch, size=12, replace=False)):
-        ref = oracle_grads(probs[i])
+    refs = oracle_map(lambda p: (oracle.solve(p), oracle_grads(p)), probs)
+    grads = {k: stack[k].grad.detach().cpu().numpy() for k in stack}
+    xs, us = x.detach().cpu().numpy(), u.detach().cpu().numpy()
+    for i, (sol, ref) in enumerate(refs):
         for k in ("A", "B", "c", "Q", "q", "R", "r", "x0"):
-            g = stack[k].grad[i].detach().cpu().numpy()
-            assert rel_err(g, ref[k]) <= FP64_TOL, (i, k)
-        sol = oracle.solve(probs[i])
-        assert rel_err(x[i].detach().cpu().numpy(), sol["x"]) <= FP64_TOL
+            assert rel_err(grads[k][i], ref[k]) <= FP64_TOL, (i, k)
+        assert rel_err(xs[i], sol["x"]) <= FP64_TOL, i
+        assert rel_err(us[i], sol["u"]) <= FP64_TOL, i
 
 
 def test_backward_matches_central_differences_of_gpu_forward():

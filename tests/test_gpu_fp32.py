@@ -3,11 +3,10 @@ matrix-core products, double factorizations and linking solve; adjoint in
 double on the staged arrays) against the FP64 oracle on the same data, at the
 1e-4 relative-error bound of the reduced-precision modes."""
 
-import numpy as np
 import pytest
 
 import oracle
-from gpu_util import MIXED_TOL, compare, host, rel_err, to_device
+from gpu_util import MIXED_TOL, compare, host, oracle_map, rel_err, to_device
 from synthetic import WORKLOADS, make_instance
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +59,9 @@ def test_fp32_backward_matches_oracle_gradient():
             assert rel_err(g[k].cpu().numpy(), ref[k]) <= MIXED_TOL, k
 
 
-def test_lqr_function_fp32_on_differentiable_workload_sample():
+def test_lqr_function_fp32_on_differentiable_workload():
+    """All 512 instances of the differentiable workload in the FP32 mode:
+    every state trajectory and every gradient against the FP64 oracle."""
     import paper_1809_06360_amd as L
     w = WORKLOADS["diff"]
     probs = [make_instance(w.cfg, i, *w.dims[i]) for i in range(w.batch)]
@@ -71,10 +72,13 @@ def test_lqr_function_fp32_on_differentiable_workload_sample():
     loss = (x * x).sum() + (u * u).sum()
     loss.backward()
     torch.cuda.synchronize()
-    rng = np.random.default_rng(13)
-    for i in sorted(rng.choice(w.batch, size=8, replace=False)):
-        sol = oracle.solve(probs[i])
-        ref = oracle.backward(probs[i], sol, 2.0 * sol["x"], 2.0 * sol["u"])
-        assert rel_err(x[i].detach().cpu().numpy(), sol["x"]) <= MIXED_TOL
+    def ref_of(p):
+        sol = oracle.solve(p)
+        return sol, oracle.backward(p, sol, 2.0 * sol["x"], 2.0 * sol["u"])
+    refs = oracle_map(ref_of, probs)
+    grads = {k: stack[k].grad.cpu().numpy() for k in keys}
+    xs = x.detach().cpu().numpy()
+    for i, (sol, ref) in enumerate(refs):
+        assert rel_err(xs[i], sol["x"]) <= MIXED_TOL, i
         for k in keys:
-            assert rel_err(stack[k].grad[i].cpu().numpy(), ref[k]) <= MIXED_TOL, (i, k)
+            assert rel_err(grads[k][i], ref[k]) <= MIXED_TOL, (i, k)

@@ -595,7 +595,17 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
       }
     }
   }
-  return __syncthreads_or(finite ? 0 : 1) ? LQR_INFO_NONFINITE : 0;
+  // any lane of any wave: one ballot per wave, met in LDS after the partial sums
+  // (no static LDS: every byte of the workgroup's LDS may be dynamic)
+  int* anybad = reinterpret_cast<int*>(smem + kWaves * 192);
+  const bool wbad = __ballot(!finite) != 0ull;
+  if (lane == 0) anybad[wave] = wbad ? 1 : 0;
+  __syncthreads();
+  int bad = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) bad |= anybad[w];
+  __syncthreads();
+  return bad ? LQR_INFO_NONFINITE : 0;
 }
 
 // Terminal value P_T = Q_T, p_T = q_T into the outputs (if requested).

@@ -225,7 +225,8 @@ LQR_HD size_t link_tree_lds(int n, int nw) {
   return dbl * 8 + (mx + 4) * 4 + 64;
 }
 
-// Partial sums of the forward simulation's matrix-vector products (n, m <= 64).
+// Partial sums of the forward simulation's matrix-vector products (n, m <= 64)
+// and one flag word per wave.
 LQR_HD size_t rollout_lds(int /*n*/, int /*m*/) { return (4 * 128 + 4 * 64) * 8 + 64; }
 
 // `nw` is the register width of the kernel variant (pad_rows of the largest n).

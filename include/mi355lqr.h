@@ -247,6 +247,26 @@ lqr_status_t lqr_backward(const lqr_problem_t *probs, int32_t batch,
 lqr_status_t lqr_workspace_layout(const lqr_problem_t *probs, int32_t batch,
                                   const lqr_options_t *opts, size_t *out);
 
+/* Bytes of the scratch array lqr_solve_noalloc uses on each device. */
+#define LQR_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* lqr_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * problem, options, kernels and results as lqr_solve, but instead of a
+ * workspace argument the call uses a scratch array of
+ * LQR_NOALLOC_SCRATCH_BYTES that the library holds on each device (placed
+ * there when the runtime loads the library's device code; it stays allocated
+ * until the process ends). The call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); its first call on a device looks up
+ * that device's copy of the array. Returns LQR_ERR_WORKSPACE if the problem
+ * needs more scratch than that (it needs at most lqr_workspace_size of the
+ * single problem), else as lqr_solve. Nothing in the array needs
+ * clearing between calls: every call writes what it reads. All calls on one
+ * device share its array, so calls that may overlap on one device (other
+ * streams, other host threads) race and must not be issued; ordering them
+ * on one stream is enough. */
+lqr_status_t lqr_solve_noalloc(const lqr_problem_t *prob, const lqr_options_t *opts, void *stream);
+
 /* Static description of a status code. */
 const char *lqr_status_string(lqr_status_t status);
 

@@ -17,8 +17,8 @@ import os
 
 __all__ = [
     "LIB_PATH", "library", "LqrProblem", "LqrOptions", "LqrGrad",
-    "lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve", "lqr_solve_phase",
-    "lqr_solve_batched", "lqr_backward", "lqr_status_string",
+    "lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve",
+    "lqr_solve_noalloc", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
     "solve", "solve_batched", "plan_segments", "backward", "LQRError",
     "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
     "INFO_COUPLING", "INFO_QUEUE", "INFO_NONFINITE", "FLAG_PHASED",
@@ -55,7 +55,9 @@ class LqrGrad(ctypes.Structure):
 
 
 EXPORTS = ("lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve",
-           "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string")
+           "lqr_solve_noalloc", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward",
+           "lqr_status_string")
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _lib = None
 
@@ -85,6 +87,8 @@ def library():
         lib.lqr_plan_segments.restype = ctypes.c_int
         lib.lqr_solve.argtypes = [P(LqrProblem), P(LqrOptions), _vp, ctypes.c_size_t, _vp]
         lib.lqr_solve.restype = ctypes.c_int
+        lib.lqr_solve_noalloc.argtypes = [P(LqrProblem), P(LqrOptions), _vp]
+        lib.lqr_solve_noalloc.restype = ctypes.c_int
         lib.lqr_solve_phase.argtypes = [P(LqrProblem), P(LqrOptions), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
         lib.lqr_solve_phase.restype = ctypes.c_int
         lib.lqr_solve_batched.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), _vp,
@@ -141,6 +145,12 @@ def lqr_solve(prob: LqrProblem, opts: LqrOptions, ws: int, ws_bytes: int, stream
     st = library().lqr_solve(ctypes.byref(prob), ctypes.byref(opts), ws, ws_bytes, stream)
     if st != SUCCESS:
         raise LQRError(st, "lqr_solve")
+
+
+def lqr_solve_noalloc(prob: LqrProblem, opts: LqrOptions, stream: int) -> None:
+    st = library().lqr_solve_noalloc(ctypes.byref(prob), ctypes.byref(opts), stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_solve_noalloc")
 
 
 def lqr_solve_phase(prob: LqrProblem, opts: LqrOptions, phase: int, ws: int, ws_bytes: int,

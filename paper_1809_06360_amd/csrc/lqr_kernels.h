@@ -27,4 +27,12 @@ hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items,
 hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, int eng, size_t lds,
                                  hipStream_t stream);
 
+// lqr_solve on a caller-given device buffer of ws_bytes (lqr_api.cpp): the
+// workspace of lqr_solve or the scratch array of lqr_solve_noalloc. Launches
+// kernels only; allocates no device memory.
+lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, void* ws,
+                          size_t ws_bytes, void* stream);
+// Device bytes solve_single needs for this problem.
+lqr_status_t solve_bytes(const lqr_problem_t* prob, const lqr_options_t* opts, size_t* bytes);
+
 }  // namespace lqr

@@ -67,8 +67,9 @@ typedef enum {
     LQR_ERR_NONFINITE = 4,        /* reserved, as above */
     LQR_ERR_WORKSPACE = 5,        /* workspace NULL or smaller than lqr_workspace_size */
     LQR_ERR_HIP = 6,              /* a HIP runtime call failed (launch, copy) */
-    LQR_ERR_UNSUPPORTED = 7       /* valid problem the library cannot run: n or m above 64,
-                                     LDS footprint above 160 KiB, mode */
+    LQR_ERR_UNSUPPORTED = 7       /* valid problem the library cannot run: n above 128 or m
+                                     above 64; an instance with more than 64 states in a
+                                     batch of several; LDS footprint above 160 KiB; mode */
 } lqr_status_t;
 
 typedef enum {

@@ -48,23 +48,41 @@ def sources():
 
 
 def _compile(src, obj, verbose):
-    cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+    cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-I", INCLUDE, "-I", CSRC, "-MMD",
+                                                             "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to an object in parallel, then link the library."""
+def _stale(src, obj):
+    """Whether obj must be rebuilt: missing, or older than its source or any
+    header listed in the dependency file the compiler wrote next to it."""
+    dep = os.path.splitext(obj)[0] + ".d"
+    if not os.path.exists(obj) or not os.path.exists(dep):
+        return True
+    t = os.path.getmtime(obj)
+    text = open(dep).read().replace("\\\n", " ")
+    paths = text.split(":", 1)[1].split() if ":" in text else [src]
+    return any(not os.path.exists(p) or os.path.getmtime(p) > t for p in paths)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the library.
+    With ``incremental`` the objects are kept in ``_build/`` next to the package
+    and only those whose source or headers changed are recompiled."""
     import concurrent.futures
     import tempfile
     srcs = sources()
     jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with tempfile.TemporaryDirectory(prefix="lqr_build_") as tmpdir:
-        objs = [os.path.join(tmpdir, os.path.basename(s_) + ".o") for s_ in srcs]
+        odir = os.path.join(ROOT, "_build") if incremental else tmpdir
+        os.makedirs(odir, exist_ok=True)
+        objs = [os.path.join(odir, os.path.basename(s_) + ".o") for s_ in srcs]
+        todo = [(s_, o) for s_, o in zip(srcs, objs) if not incremental or _stale(s_, o)]
         with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-            list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))
+            list(ex.map(lambda so: _compile(so[0], so[1], verbose), todo))
         tmp = LIB + ".tmp%d" % os.getpid()
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
         if verbose:
@@ -75,5 +93,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

@@ -261,6 +261,11 @@ struct k_link_maps_ref {
   static auto fn() { return &k_link_maps<W, M>; }
 };
 
+hipError_t launch_link_init(const InstDesc& d, hipStream_t stream) {
+  hipLaunchKernelGGL(k_link_init, dim3(d.J), dim3(kThreads), 0, stream, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
   const int J = d.J, n = d.n;
   hipLaunchKernelGGL(k_link_init, dim3(J), dim3(kThreads), 0, stream, d);

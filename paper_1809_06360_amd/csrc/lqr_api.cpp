@@ -114,6 +114,7 @@ struct BatchPlan {
   size_t total_bytes = 0;
   int nitems = 0;
   int max_n = 1, max_m = 1;
+  bool big = false;  // one instance with 65..128 states: the large-state kernels
   size_t lds1 = 0, lds2 = 0, lds3 = 0, lds_serial = 0, lds_persist = 0;
 };
 
@@ -121,6 +122,9 @@ bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL;
 bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
 bool is_mixed(const lqr_options_t* o) { return o && o->precision == LQR_PREC_MIXED; }
 bool is_f32(const lqr_options_t* o) { return o && o->precision == LQR_PREC_FP32; }
+// Product engine of the large-state kernels: FP32 matrix cores in the mixed and
+// FP32 modes, FP64 matrix cores otherwise.
+int big_engine(const lqr_options_t* o) { return (is_mixed(o) || is_f32(o)) ? 2 : 1; }
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
@@ -150,6 +154,40 @@ lqr_status_t check_pointers(const lqr_problem_t& p) {
 // per lane, so one 256-thread workgroup fills a compute unit whatever its LDS.
 int planned_slots(size_t /*lds*/) { return kComputeUnits; }
 
+// Segments of a large-state instance when the caller leaves the choice to the
+// planner: about 16 stages each (the dual sweep's extra work against the
+// logarithmic-depth linking solve), at most 256.
+int big_segments(int T) { return std::max(1, std::min(256, std::min(T, (T + 8) / 16))); }
+
+// Plan of one instance with 65..128 states (at most 64 inputs): the
+// large-state kernels, one 512-thread workgroup per segment.
+lqr_status_t build_big_plan(const lqr_problem_t& p, const lqr_options_t* opts, BatchPlan* plan) {
+  plan->big = true;
+  plan->max_n = p.n;
+  plan->max_m = p.m;
+  const int J = is_serial(opts) ? 1 : (p.segments > 0 ? p.segments : big_segments(p.T));
+  plan->inst[0].J = J;
+  plan->nitems = J;
+  plan->lds1 = plan->lds3 = plan->lds_serial = big_sweep_lds();
+  plan->lds2 = big_link_lds();
+  plan->reg = regions_of(&p, 1);
+  plan->table_off = plan->reg.fwd_off;
+  plan->items_off = plan->tasks_off = plan->cvt_off = plan->table_off;
+  plan->table_bytes = 0;
+  plan->sync_off = plan->reg.scratch_off;
+  size_t off = plan->sync_off + align_up(sizeof(int32_t) * sync_words(1));
+  if (is_f32(opts)) {
+    plan->inst[0].stage_off = off;
+    off += align_up((stage_in_doubles(p.n, p.m, p.T) + stage_out_doubles(p.n, p.m, p.T)) * sizeof(double));
+  }
+  const size_t bytes = align_up(big_ws_doubles(p.n, p.m, J) * sizeof(double)) +
+                       align_up(sizeof(int32_t) * fail_words(J));
+  plan->inst[0].ws_off = off;
+  plan->inst[0].ws_bytes = bytes;
+  plan->total_bytes = off + bytes;
+  return LQR_SUCCESS;
+}
+
 lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options_t* opts,
                         BatchPlan* plan) {
   lqr_status_t st = check_options(opts);
@@ -162,8 +200,11 @@ lqr_status_t build_plan(const lqr_problem_t* probs, int batch, const lqr_options
   for (int i = 0; i < batch; ++i) {
     const lqr_problem_t& p = probs[i];
     if ((st = check_dims(p)) != LQR_SUCCESS) return st;
-    // register-resident columns and rows of the kernels (elimination, simulation)
-    if (p.n > 64 || p.m > 64) return LQR_ERR_UNSUPPORTED;
+    if (p.n > 64 || p.m > 64) {
+      // the large-state kernels: single instances of up to 128 states and 64 inputs
+      if (!is_big(p.n, p.m) || batch != 1) return LQR_ERR_UNSUPPORTED;
+      return build_big_plan(p, opts, plan);
+    }
     plan->max_n = std::max(plan->max_n, p.n);
     plan->max_m = std::max(plan->max_m, p.m);
   }
@@ -363,7 +404,8 @@ InstDesc make_desc(const lqr_problem_t& p, int J, char* ws_base, size_t ws_off) 
   d.chol = static_cast<double*>(p.chol);
   d.info = p.info;
   d.ws = reinterpret_cast<double*>(ws_base + ws_off);
-  d.fail = reinterpret_cast<int32_t*>(ws_base + ws_off + align_up(ws_doubles(p.n, J) * sizeof(double)));
+  const size_t wsd = is_big(p.n, p.m) ? big_ws_doubles(p.n, p.m, J) : ws_doubles(p.n, J);
+  d.fail = reinterpret_cast<int32_t*>(ws_base + ws_off + align_up(wsd * sizeof(double)));
   return d;
 }
 
@@ -538,9 +580,21 @@ lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, 
     d = make_desc(*prob, plan.inst[0].J, static_cast<char*>(ws), plan.inst[0].ws_off);
   }
   hipError_t e = launch_convert_list(cin, s);
-  if (e == hipSuccess)
-    e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
-                        : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+  if (e == hipSuccess) {
+    if (plan.big) {
+      const int beng = big_engine(opts);
+      if (is_serial(opts)) {
+        e = launch_big_sweep(d, 0, beng, plan.lds_serial, s);
+      } else {
+        e = launch_big_sweep(d, 1, beng, plan.lds1, s);
+        if (e == hipSuccess) e = launch_big_link(d, plan.lds2, s);
+        if (e == hipSuccess) e = launch_big_sweep(d, 3, beng, plan.lds3, s);
+      }
+    } else {
+      e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
+                          : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+    }
+  }
   if (e == hipSuccess) e = launch_convert_list(cout, s);
   return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
 }
@@ -641,7 +695,16 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     const int eng = launch_engine(plan.max_n, is_mixed(opts));
-    if (is_serial(opts)) {
+    if (plan.big) {
+      const int beng = big_engine(opts);
+      if (is_serial(opts)) {
+        if (phase == 1) e = launch_big_sweep(d, 0, beng, plan.lds_serial, s);
+      } else if (phase == 2) {
+        e = launch_big_link(d, plan.lds2, s);
+      } else {
+        e = launch_big_sweep(d, phase, beng, phase == 1 ? plan.lds1 : plan.lds3, s);
+      }
+    } else if (is_serial(opts)) {
       if (phase == 1) e = launch_serial(d, plan.lds_serial, eng, s);
     } else {
       const size_t lds = phase == 1 ? plan.lds1 : phase == 2 ? plan.lds2 : plan.lds3;
@@ -674,6 +737,8 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     BatchPlan plan;
     lqr_status_t st = make_plan(probs, batch, opts, &plan);
     if (st != LQR_SUCCESS) return st;
+    // a large-state instance (batch of one): the single-instance launches
+    if (plan.big) return solve_single(probs, opts, ws, ws_bytes, stream);
     for (int i = 0; i < batch; ++i)
       if ((st = check_pointers(probs[i])) != LQR_SUCCESS) return st;
     if ((st = check_device(plan)) != LQR_SUCCESS) return st;

@@ -97,6 +97,17 @@ hipError_t launch_persistent(const InstDesc* descs, const TaskItem* tasks, int n
 // states. lds: link_tree_lds of the instance.
 hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream);
 
+// First launch of the logarithmic-depth linking solve: scan buffer 0 from the
+// phase-1 summaries and the last segment's value (k_link_tree.hip).
+hipError_t launch_link_init(const InstDesc& d, hipStream_t stream);
+
+// Large-state path (65..128 states, big_device.h): the sweep kernels of
+// engine eng (1: FP64, 2: FP32 matrix cores) -- kind 1 phase 1, kind 3 phase 3
+// (d.J workgroups), kind 0 the plain serial recursion (one workgroup) -- and
+// the FP64 linking solve (any J >= 1). lds: big_sweep_lds / big_link_lds.
+hipError_t launch_big_sweep(const InstDesc& d, int kind, int eng, size_t lds, hipStream_t stream);
+hipError_t launch_big_link(const InstDesc& d, size_t lds, hipStream_t stream);
+
 // FP32 mode conversions: the arrays of a device table (one block column per
 // array), or a by-value list of one instance's arrays.
 hipError_t launch_convert(const CvtItem* items, int nitems, hipStream_t stream);

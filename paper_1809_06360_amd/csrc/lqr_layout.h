@@ -225,6 +225,41 @@ LQR_HD size_t link_tree_lds(int n, int nw) {
   return dbl * 8 + (mx + 4) * 4 + 64;
 }
 
+// ---------------------------------------------------------------------------
+// Large-state path (65..128 states, up to 64 inputs; 512-thread workgroups).
+// ---------------------------------------------------------------------------
+constexpr int kBigMaxN = 128;
+constexpr int kBigMaxM = 64;
+LQR_HD bool is_big(int n, int m) { return n > 64 && n <= kBigMaxN && m <= kBigMaxM; }
+
+// Sweep scratch of one segment, in doubles (sized for double elements; the
+// FP32-product engine stores float and uses half): P (n x n) | Y = P[B | A | c]
+// (n x (m+n+1)) | Gamma, twice (n x n each) | Psi (n x n) | right-hand sides
+// and their eliminated form Z (m x (2n+1) each).
+LQR_HD size_t big_sweep_doubles(int n, int m) {
+  const size_t nn = (size_t)n * n;
+  return nn + (size_t)n * (m + n + 1) + 2 * nn + nn + 2 * (size_t)m * (2 * n + 1);
+}
+// Join scratch of one scan element: four n x n products.
+LQR_HD size_t big_join_doubles(int n) { return 4 * (size_t)n * n; }
+// Per-instance workspace of the large-state path: that of ws_doubles, then J
+// sweep scratches, then J join scratches.
+LQR_HD size_t big_ws_doubles(int n, int m, int J) {
+  return ws_doubles(n, J) + (size_t)J * (big_sweep_doubles(n, m) + big_join_doubles(n));
+}
+LQR_HD double* big_sweep_ws(double* ws, int n, int m, int J, int seg) {
+  return ws + ws_doubles(n, J) + (size_t)seg * big_sweep_doubles(n, m);
+}
+LQR_HD double* big_join_ws(double* ws, int n, int m, int J, int j) {
+  return ws + ws_doubles(n, J) + (size_t)J * big_sweep_doubles(n, m) + (size_t)j * big_join_doubles(n);
+}
+// LDS of the large-state sweeps: the input Hessian and L^{-1} (m x 65 doubles
+// each, column-major), the elimination's exchange vector, five n-vectors and
+// flag words; of the forward simulation: x, u; of the linking kernels: an
+// n x (n+1) matrix, exchange space, pivot maps and four n-vectors.
+LQR_HD size_t big_sweep_lds() { return (2 * 64 * 65 + 3 * 64 + 5 * 128) * 8 + 64; }
+LQR_HD size_t big_link_lds() { return (128 * 129 + 512 + 4 * 128) * 8 + 256 * 4 + 64; }
+
 // Partial sums of the forward simulation's matrix-vector products (n, m <= 64)
 // and one flag word per wave.
 LQR_HD size_t rollout_lds(int /*n*/, int /*m*/) { return (4 * 128 + 4 * 64) * 8 + 64; }

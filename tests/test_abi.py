@@ -121,15 +121,31 @@ def test_solve_rejects_null_pointers_and_small_workspace():
     assert e.value.status == L.ERR_WORKSPACE
 
 
-@pytest.mark.parametrize("n,m", [(65, 4), (8, 65), (65, 65)])
-def test_states_or_inputs_above_64_are_unsupported(n, m):
-    """The kernels hold up to 64 state and input rows in registers (the
-    elimination's columns, the forward simulation's rows); larger problems are
+@pytest.mark.parametrize("n,m", [(129, 4), (8, 65), (65, 65), (200, 100)])
+def test_sizes_beyond_the_kernels_are_unsupported(n, m):
+    """Up to 64 inputs (the input Hessian's factorization holds a column per
+    lane) and up to 128 states (the large-state kernels); larger problems are
     rejected at planning time, for every algorithm."""
     for algo in ("parallel", "serial"):
         with pytest.raises(L.LQRError) as e:
             L.lqr_workspace_size(ctypes.byref(_prob(n, m, 16, 0)), 1, L.options(algo=algo))
         assert e.value.status == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,m,T,J", [(65, 4, 16, 0), (128, 64, 2048, 128), (100, 1, 7, 7), (128, 64, 40, 1)])
+def test_large_state_instances_are_planned_alone(n, m, T, J):
+    """65..128 states run the large-state kernels: a single instance (through
+    lqr_solve, or lqr_solve_batched with a batch of one) for every precision
+    and algorithm; in a batch with other instances it is refused."""
+    for prec in ("fp64", "mixed", "fp32"):
+        for algo in ("parallel", "serial"):
+            assert L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, J)), 1, L.options(prec, algo)) > 0
+    (got,), _ = L.lqr_plan_segments(ctypes.byref(_prob(n, m, T, J)), 1, L.options())
+    assert got == (J if J else max(1, min(256, T, (T + 8) // 16)))
+    arr = (L.LqrProblem * 2)(_prob(n, m, T, J), _prob(8, 4, 32, 0))
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_workspace_size(arr, 2, L.options())
+    assert e.value.status == L.ERR_UNSUPPORTED
 
 
 def test_oversized_problem_is_unsupported_not_crashing():
@@ -142,10 +158,10 @@ def test_every_named_workload_fits_the_device_limits():
     """The planner accepts every instance of the named workloads (LDS
     footprints within the 160 KiB a gfx950 workgroup may allocate)."""
     from synthetic import WORKLOADS
-    for key in ("small", "large", "batched", "diff"):
+    for key in ("small", "large", "batched", "mixed", "diff"):
         w = WORKLOADS[key]
         arr = (L.LqrProblem * w.batch)(*[L.LqrProblem(n, m, T, w.segments) for (n, m, T) in w.dims])
-        assert L.lqr_workspace_size(arr, w.batch, L.options()) > 0, key
+        assert L.lqr_workspace_size(arr, w.batch, L.options(w.precision)) > 0, key
 
 
 def test_backward_rejects_bad_arguments():
@@ -193,7 +209,8 @@ def test_planner_splits_long_single_instances_more_than_short_ones():
 
 def test_precision_modes():
     """FP64 and mixed precision plan the same workspace; FP32 adds the staging
-    area; the mixed-precision workload (n = 128) does not fit the kernels."""
+    area; the mixed-precision workload (n = 128, m = 64, T = 2048, J = 128)
+    is planned with its 128 segments."""
     a = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("fp64"))
     b = L.lqr_workspace_size(ctypes.byref(_prob(48, 24, 1024, 64)), 1, L.options("mixed"))
     assert a == b
@@ -208,10 +225,10 @@ def test_precision_modes():
     assert e.value.status == L.ERR_UNSUPPORTED
     from synthetic import WORKLOADS
     (n, m, T), = WORKLOADS["mixed"].dims
-    with pytest.raises(L.LQRError) as e:
-        L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, WORKLOADS["mixed"].segments)), 1,
-                             L.options("mixed"))
-    assert e.value.status == L.ERR_UNSUPPORTED
+    J = WORKLOADS["mixed"].segments
+    assert L.lqr_workspace_size(ctypes.byref(_prob(n, m, T, J)), 1, L.options("mixed")) > 0
+    (got,), _ = L.lqr_plan_segments(ctypes.byref(_prob(n, m, T, J)), 1, L.options("mixed"))
+    assert got == J == 128
 
 
 @pytest.mark.parametrize("dims", [

@@ -4,11 +4,11 @@
 // sweep, the linking solve, a rebuild from the exact boundary values and the
 // forward simulation (Sec. II-A) -- laid out for blocks that no longer fit the
 // LDS: a 128 x 128 value Hessian alone takes 64 KiB in float and 128 KiB in
-// double. Each segment's workgroup (512 threads) keeps its n x n matrices
+// double. Each segment's workgroup (256 threads) keeps its n x n matrices
 // (P, Gamma, Psi), the stage products Y = P[B | A | c] and the eliminated
 // right-hand sides in its slice of the workspace, where they stay in the L2
-// cache, and feeds the matrix cores from there; the LDS holds the input
-// Hessian (FP64), its inverse factor and the vectors.
+// cache, and feeds the matrix cores through LDS panels (bmm); the LDS also
+// holds the input Hessian (FP64), its inverse factor and the vectors.
 //
 // Engine E: 2 = FP32 matrix cores with float accumulation and float storage
 // of the products (mixed-precision mode), 1 = FP64 matrix cores and double
@@ -35,12 +35,12 @@ struct SweepL {
 
 LQR_DEV SweepL carve_lds(double* smem) {
   SweepL s;
-  s.H = smem;                     // m x m column-major, ld kLdH
+  s.H = smem + kPanelBytes / sizeof(double);  // m x m column-major, ld kLdH (after the panels)
   s.Linv = s.H + 64 * kLdH;       // L^{-1}, column-major, ld kLdH
   s.ex = s.Linv + 64 * kLdH;      // 3 x 64 elimination exchange
   s.p = s.ex + 3 * 64;            // value gradient (n)
   s.psi = s.p + 128;              // psi (n)
-  s.gc = s.psi + 128;             // Gamma' c (n)
+  s.gc = s.psi + 128;             // Gamma' c (n), then 256 doubles of reduction space
   s.flags = reinterpret_cast<int*>(s.gc + 3 * 128);
   return s;
 }
@@ -133,11 +133,11 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const T* Y, const T* Z, int l
       SkipUpper{n});
 }
 
-// Factor the input Hessian (FP64, column-owner LDL' in one wave) and form
-// L^{-1}; then Z = L^{-1} RHS (nc columns) on the engine's matrix cores.
+// Factor the input Hessian and form L^{-1} (FP64, blocked, chol_inv64); then
+// Z = L^{-1} RHS (nc columns) on the engine's matrix cores.
 template <int E, typename T>
 LQR_DEV void stage_eliminate(int m, int nc, const SweepL& s, double* chol, const T* RHS, int ldr, T* Z) {
-  ldl_columns<64>(s.H, kLdH, m, 0, true, s.Linv, kLdH, chol, s.ex, s.flags);
+  chol_inv64(s.H, kLdH, m, s.Linv, kLdH, chol, s.flags);
   bmm1<E, true, false>(m, nc, m, s.Linv, kLdH, RHS, ldr,
                        [=](int i, int j, double v) { Z[i * ldr + j] = (T)v; });
 }
@@ -158,7 +158,7 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
     s.flags[1] = 0;
   }
   bcopy(w.P, n, Pend, n, n, n);
-  for (int i = threadIdx.x; i < n; i += kBT) s.p[i] = pend[i];
+  for (int i = threadIdx.x; i < n; i += nthreads()) s.p[i] = pend[i];
   __syncthreads();
   int fail = 0;
   for (int t = t1 - 1; t >= t0; --t) {
@@ -203,7 +203,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, double* s
   bfill(w.P, n, n, n, T(0), T(0));
   bfill(w.Psi, n, n, n, T(0), T(0));
   bfill(w.Ga, n, n, n, T(0), T(1));
-  for (int i = threadIdx.x; i < n; i += kBT) {
+  for (int i = threadIdx.x; i < n; i += nthreads()) {
     s.p[i] = 0.0;
     s.psi[i] = 0.0;
   }
@@ -216,7 +216,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, double* s
     const double* ct = d.c + (size_t)t * n;
     stage_y<E>(d, t, w.P, s.p, w.Y);
     double* gc = s.gc;
-    bgemv_t(n, n, Gam, n, ct, [=](int j, double v) { gc[j] = v; });  // Gam' c
+    bgemv_t(n, n, Gam, n, ct, gc + 128, [=](int j, double v) { gc[j] = v; });  // Gam' c
     __syncthreads();
     stage_h<E>(d, t, w.Y, Gam, s.H, w.R, ldr);
     __syncthreads();
@@ -252,7 +252,7 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, double* s
   bcopy(out, n, w.P, n, n, n);
   bcopy(out + nn, n, Gam, n, n, n);
   bcopy(out + 2 * nn, n, w.Psi, n, n, n);
-  for (int i = threadIdx.x; i < n; i += kBT) {
+  for (int i = threadIdx.x; i < n; i += nthreads()) {
     out[3 * nn + i] = s.p[i];
     out[3 * nn + n + i] = s.psi[i];
   }
@@ -271,13 +271,13 @@ LQR_DEV int roll_forward(const InstDesc& d, int t0, int t1, const double* xs, bo
   int* flag = reinterpret_cast<int*>(su + 64);
   const bool want_lam = d.lam != nullptr;
   if (threadIdx.x == 0) flag[0] = 0;
-  for (int i = threadIdx.x; i < n; i += kBT) sx[i] = xs[i];
+  for (int i = threadIdx.x; i < n; i += nthreads()) sx[i] = xs[i];
   __syncthreads();
   int cur = 0;
   for (int t = t0; t < t1; ++t) {
     const double* x = sx + cur * 128;
     double* xn = sx + (1 - cur) * 128;
-    for (int i = threadIdx.x; i < n; i += kBT) {
+    for (int i = threadIdx.x; i < n; i += nthreads()) {
       d.x[(size_t)t * n + i] = x[i];
       if (!isfinite(x[i])) flag[0] = 1;
     }
@@ -302,7 +302,7 @@ LQR_DEV int roll_forward(const InstDesc& d, int t0, int t1, const double* xs, bo
     const double* ct = d.c + (size_t)t * n;
     {  // x' = A x + B u + c: eight lanes per row
       const int sub = threadIdx.x & 7;
-      for (int i = threadIdx.x >> 3; i < n; i += kBT >> 3) {
+      for (int i = threadIdx.x >> 3; i < n; i += nthreads() >> 3) {
         double a = 0.0;
         for (int l = sub; l < n; l += 8) a = fma(At[(size_t)i * n + l], x[l], a);
         for (int l = sub; l < m; l += 8) a = fma(Bt[(size_t)i * m + l], su[l], a);
@@ -317,7 +317,7 @@ LQR_DEV int roll_forward(const InstDesc& d, int t0, int t1, const double* xs, bo
   }
   if (last) {
     const double* x = sx + cur * 128;
-    for (int i = threadIdx.x; i < n; i += kBT) {
+    for (int i = threadIdx.x; i < n; i += nthreads()) {
       d.x[(size_t)T * n + i] = x[i];
       if (!isfinite(x[i])) flag[0] = 1;
     }
@@ -341,7 +341,7 @@ LQR_DEV void store_terminal(const InstDesc& d) {
   const int n = d.n, T = d.T;
   if (d.P) bcopy(d.P + (size_t)T * n * n, n, d.Q + (size_t)T * n * n, n, n, n);
   if (d.p)
-    for (int i = threadIdx.x; i < n; i += kBT) d.p[(size_t)T * n + i] = d.q[(size_t)T * n + i];
+    for (int i = threadIdx.x; i < n; i += nthreads()) d.p[(size_t)T * n + i] = d.q[(size_t)T * n + i];
 }
 
 template <int E>
@@ -359,7 +359,7 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
     const SweepL s = carve_lds(smem);
     double* b = ws_bnd(d.ws, n, J, J - 1);
     bcopy(b, n, w.P, n, n, n);
-    for (int i = threadIdx.x; i < n; i += kBT) b[n * n + i] = s.p[i];
+    for (int i = threadIdx.x; i < n; i += nthreads()) b[n * n + i] = s.p[i];
   }
   if (threadIdx.x == 0) d.fail[seg] = fail;
 }

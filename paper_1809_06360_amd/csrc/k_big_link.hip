@@ -26,17 +26,15 @@ LQR_DEV double* elem(const double* buf, int n, int j) {
   return const_cast<double*>(buf) + (size_t)j * seg_stride(n);
 }
 
+// LDS after the product panels: the inverse's exchange space, vectors, pivot maps.
 struct LinkL {
-  double *E, *xb, *w1, *w2, *e2;
+  double *xb, *w1, *w2, *e2;
   int *rowof, *flag;
-  int ld;
 };
 
-LQR_DEV LinkL carve_link(double* smem, int n) {
+LQR_DEV LinkL carve_link(double* smem) {
   LinkL s;
-  s.ld = n + 1;
-  s.E = smem;
-  s.xb = s.E + n * s.ld;
+  s.xb = smem + big::kPanelBytes / sizeof(double);
   s.w1 = s.xb + 512;
   s.w2 = s.w1 + 128;
   s.e2 = s.w2 + 128;
@@ -64,38 +62,38 @@ __global__ __launch_bounds__(kBT) void k_big_link_combine(InstDesc d, int dist, 
   const double *P0a = a, *Ga = a + nn, *Psa = a + 2 * nn, *pa = a + 3 * nn, *psa = pa + n;
   const double *P0b = b, *Gb = b + nn, *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
   double *oP0 = o, *oG = o + nn, *oPs = o + 2 * nn, *op = o + 3 * nn, *ops = op + n;
-  const LinkL s = carve_link(smem, n);
-  double* E = s.E;
-  const int ld = s.ld;
+  const LinkL s = carve_link(smem);
   double* F = big_join_ws(d.ws, n, d.m, J, j);
   double* G1 = F + nn;
   double* V = G1 + nn;
   double* U = V + nn;
+  double* E = U + nn;  // M, then M^{-1} (row-major, leading dimension ld)
+  const int ld = n;
   if (threadIdx.x == 0) *s.flag = 0;
   // M = I + P0_b Psi_a (P0_b symmetric: read transposed for coalesced loads)
-  bmm1<1, true, false>(n, n, n, P0b, n, Psa, n,
+  bmm1<1, true, false, kBT>(n, n, n, P0b, n, Psa, n,
                        [=](int i, int c, double v) { E[i * ld + c] = v + (i == c ? 1.0 : 0.0); });
   __syncthreads();
   big::gj_invert(E, ld, n, s.xb, s.rowof, s.flag);
   double* w1 = s.w1;
   double* w2 = s.w2;
   double* e2 = s.e2;
-  bmm1<1, false, false>(n, n, n, Ga, n, E, ld, [=](int i, int c, double v) { F[i * n + c] = v; });
+  bmm1<1, false, false, kBT>(n, n, n, Ga, n, E, ld, [=](int i, int c, double v) { F[i * n + c] = v; });
   bgemv(n, n, P0b, n, psa, [=](int i, double v) { w1[i] = pb[i] + v; });
   if (!exact_b) {
-    bmm1<1, true, false>(n, n, n, Psa, n, Gb, n, [=](int i, int c, double v) { V[i * n + c] = v; });
+    bmm1<1, true, false, kBT>(n, n, n, Psa, n, Gb, n, [=](int i, int c, double v) { V[i * n + c] = v; });
     bgemv(n, n, Psa, n, pb, [=](int i, double v) { w2[i] = psa[i] - v; });
   }
   __syncthreads();
-  bmm1<1, false, false>(n, n, n, F, n, P0b, n, [=](int i, int c, double v) { G1[i * n + c] = v; });
+  bmm1<1, false, false, kBT>(n, n, n, F, n, P0b, n, [=](int i, int c, double v) { G1[i * n + c] = v; });
   bgemv(n, n, F, n, w1, [=](int i, double v) { op[i] = pa[i] + v; });
   if (!exact_b) {
-    bmm1<1, false, false>(n, n, n, F, n, Gb, n, [=](int i, int c, double v) { oG[i * n + c] = v; });
-    bmm1<1, true, false>(n, n, n, E, ld, V, n, [=](int i, int c, double v) { U[i * n + c] = v; });
-    bgemv_t(n, n, E, ld, w2, [=](int c, double v) { e2[c] = v; });
+    bmm1<1, false, false, kBT>(n, n, n, F, n, Gb, n, [=](int i, int c, double v) { oG[i * n + c] = v; });
+    bmm1<1, true, false, kBT>(n, n, n, E, ld, V, n, [=](int i, int c, double v) { U[i * n + c] = v; });
+    bgemv_t(n, n, E, ld, w2, s.xb, [=](int c, double v) { e2[c] = v; });
   }
   __syncthreads();
-  bmm1<1, false, true>(n, n, n, G1, n, Ga, n,
+  bmm1<1, false, true, kBT>(n, n, n, G1, n, Ga, n,
       [=](int i, int c, double v) {
         if (i >= c) {
           v += 0.5 * (P0a[i * n + c] + P0a[c * n + i]);
@@ -105,7 +103,7 @@ __global__ __launch_bounds__(kBT) void k_big_link_combine(InstDesc d, int dist, 
       },
       SkipUpper{n});
   if (!exact_b) {
-    bmm1<1, true, false>(n, n, n, Gb, n, U, n,
+    bmm1<1, true, false, kBT>(n, n, n, Gb, n, U, n,
         [=](int i, int c, double v) {
           if (i >= c) {
             v += 0.5 * (Psb[i * n + c] + Psb[c * n + i]);
@@ -114,7 +112,7 @@ __global__ __launch_bounds__(kBT) void k_big_link_combine(InstDesc d, int dist, 
           }
         },
         SkipUpper{n});
-    bgemv_t(n, n, Gb, n, e2, [=](int c, double v) { ops[c] = psb[c] + v; });
+    bgemv_t(n, n, Gb, n, e2, s.xb, [=](int c, double v) { ops[c] = psb[c] + v; });
   }
   __syncthreads();
   if (threadIdx.x == 0 && *s.flag) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
@@ -136,18 +134,18 @@ __global__ __launch_bounds__(kBT) void k_big_link_maps(InstDesc d, const double*
   const double *Pn = nx, *pn = nx + 3 * nn;
   const double* sg = ws_seg(d.ws, n, j);
   const double *Gam = sg + nn, *Psi = sg + 2 * nn, *psi = sg + 3 * nn + n;
-  const LinkL s = carve_link(smem, n);
-  double* E = s.E;
-  const int ld = s.ld;
+  const LinkL s = carve_link(smem);
+  double* E = big_join_ws(d.ws, n, d.m, J, j) + 4 * (size_t)nn;  // N, then N^{-1}
+  const int ld = n;
   double* w = s.w1;
   if (threadIdx.x == 0) *s.flag = 0;
-  bmm1<1, true, false>(n, n, n, Psi, n, Pn, n,
+  bmm1<1, true, false, kBT>(n, n, n, Psi, n, Pn, n,
                        [=](int i, int c, double v) { E[i * ld + c] = v + (i == c ? 1.0 : 0.0); });
   bgemv(n, n, Psi, n, pn, [=](int i, double v) { w[i] = psi[i] - v; });
   __syncthreads();
   big::gj_invert(E, ld, n, s.xb, s.rowof, s.flag);
   double* lk = ws_link(d.ws, n, J, j);
-  bmm1<1, false, true>(n, n, n, E, ld, Gam, n, [=](int i, int c, double v) { lk[i * n + c] = v; });
+  bmm1<1, false, true, kBT>(n, n, n, E, ld, Gam, n, [=](int i, int c, double v) { lk[i * n + c] = v; });
   bgemv(n, n, E, ld, w, [=](int i, double v) { lk[nn + i] = v; });
   __syncthreads();
   if (threadIdx.x == 0 && *s.flag) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);

@@ -160,7 +160,7 @@ int planned_slots(size_t /*lds*/) { return kComputeUnits; }
 int big_segments(int T) { return std::max(1, std::min(256, std::min(T, (T + 8) / 16))); }
 
 // Plan of one instance with 65..128 states (at most 64 inputs): the
-// large-state kernels, one 512-thread workgroup per segment.
+// large-state kernels, one 256-thread workgroup per segment.
 lqr_status_t build_big_plan(const lqr_problem_t& p, const lqr_options_t* opts, BatchPlan* plan) {
   plan->big = true;
   plan->max_n = p.n;

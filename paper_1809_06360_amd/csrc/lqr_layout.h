@@ -226,7 +226,8 @@ LQR_HD size_t link_tree_lds(int n, int nw) {
 }
 
 // ---------------------------------------------------------------------------
-// Large-state path (65..128 states, up to 64 inputs; 512-thread workgroups).
+// Large-state path (65..128 states, up to 64 inputs; 256-thread sweep and
+// 512-thread linking workgroups).
 // ---------------------------------------------------------------------------
 constexpr int kBigMaxN = 128;
 constexpr int kBigMaxM = 64;
@@ -240,8 +241,9 @@ LQR_HD size_t big_sweep_doubles(int n, int m) {
   const size_t nn = (size_t)n * n;
   return nn + (size_t)n * (m + n + 1) + 2 * nn + nn + 2 * (size_t)m * (2 * n + 1);
 }
-// Join scratch of one scan element: four n x n products.
-LQR_HD size_t big_join_doubles(int n) { return 4 * (size_t)n * n; }
+// Join scratch of one scan element: four n x n products and the inverted
+// linking matrix.
+LQR_HD size_t big_join_doubles(int n) { return 5 * (size_t)n * n; }
 // Per-instance workspace of the large-state path: that of ws_doubles, then J
 // sweep scratches, then J join scratches.
 LQR_HD size_t big_ws_doubles(int n, int m, int J) {
@@ -253,12 +255,15 @@ LQR_HD double* big_sweep_ws(double* ws, int n, int m, int J, int seg) {
 LQR_HD double* big_join_ws(double* ws, int n, int m, int J, int j) {
   return ws + ws_doubles(n, J) + (size_t)J * big_sweep_doubles(n, m) + (size_t)j * big_join_doubles(n);
 }
-// LDS of the large-state sweeps: the input Hessian and L^{-1} (m x 65 doubles
-// each, column-major), the elimination's exchange vector, five n-vectors and
-// flag words; of the forward simulation: x, u; of the linking kernels: an
-// n x (n+1) matrix, exchange space, pivot maps and four n-vectors.
-LQR_HD size_t big_sweep_lds() { return (2 * 64 * 65 + 3 * 64 + 5 * 128) * 8 + 64; }
-LQR_HD size_t big_link_lds() { return (128 * 129 + 512 + 4 * 128) * 8 + 256 * 4 + 64; }
+// LDS of the large-state kernels: first the two panel buffers of their
+// matrix-core products (kBigPanelBytes), then for the sweeps the input Hessian
+// and L^{-1} (m x 65 doubles each, column-major), the elimination's exchange
+// vector, five n-vectors and flag words (the forward simulation reuses the
+// start: x, u); for the linking kernels the inverse's exchange space, four
+// n-vectors and the pivot maps.
+constexpr size_t kBigPanelBytes = 68608;
+LQR_HD size_t big_sweep_lds() { return kBigPanelBytes + (2 * 64 * 65 + 3 * 64 + 5 * 128) * 8 + 64; }
+LQR_HD size_t big_link_lds() { return kBigPanelBytes + (512 + 4 * 128) * 8 + 256 * 4 + 64; }
 
 // Partial sums of the forward simulation's matrix-vector products (n, m <= 64)
 // and one flag word per wave.

@@ -51,12 +51,20 @@ __global__ __launch_bounds__(kThreads) void k_link_init(InstDesc d) {
 
 // One scan round: out[j] = in[j] (x) in[j + dist], or in[j] when j + dist >= J
 // (then in[j] already reaches the last segment and only its P0, pbar are used).
+// The join works from the explicit inverse Mi = M^{-1} (one wave, see
+// wave_invert) and the identities X1 = Mi P0_b Gam_a', X3 = Mi Gam_b and
+// Mi' Psi_a = Psi_a Mi (so V = Psi_a Mi is symmetric):
+//   P0_ab  = P0_a + Y R,      Y = Gam_a Mi,  R = P0_b Gam_a'
+//   pbar_ab = pbar_a + Gam_a Mi (P0_b psi_a + pbar_b)
+//   Gam_ab = Y Gam_b,         Psi_ab = Psi_b + Gam_b' (V Gam_b)
+//   psi_ab = psi_b + Gam_b' Mi' (psi_a - Psi_a pbar_b)
+// Work blocks in LDS are n x ld_odd(n); row-major unless noted.
 template <int MN, int E>
 __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist, const double* in,
                                                            double* out) {
   extern __shared__ double smem[];
   const int n = d.n, J = d.J, j = blockIdx.x;
-  const int nn = n * n;
+  const int nn = n * n, L = ld_odd(n), blk = n * L;
   const double* a = scan_elem(const_cast<double*>(in), n, j);
   double* o = scan_elem(out, n, j);
   if (j + dist >= J) {
@@ -69,48 +77,64 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
   const double *P0a = a, *pa = a + 3 * nn, *psa = pa + n;
   const double *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
   const double *Ga = a + nn, *Psa = a + 2 * nn, *P0b = b, *Gb = b + nn;
-  const int mp = MN + 1;
-  const int nc = exact_b ? 2 * n + 1 : 3 * n + 1;
-  double* sN = smem;                     // mp x nc column-major: [M | RHS] -> [. | X1 | x2 | X3]
-  double* sW = sN + mp * (3 * n + 1);    // n x n row-major: Psi_a Gam_b
-  double* sv = sW + nn;                  // psi_a - Psi_a pbar_b
-  double* gjb = sv + n;
-  int* prow = reinterpret_cast<int*>(gjb + 3 * MN + 2);
-  int* flag = prow + MN;
+  int lg = n;  // leading dimension of the four operands
+  double* sM = smem;       // M, column-major -> Mi in place -> U = V Gam_b
+  double* sR = sM + blk;   // R = P0_b Gam_a'
+  double* sY = sR + blk;   // Y = Gam_a Mi
+  double* sV = sY + blk;   // V = Psi_a Mi
+  double* r2 = sV + blk;   // P0_b psi_a + pbar_b
+  double* sv = r2 + n;     // psi_a - Psi_a pbar_b
+  double* su = sv + n;     // Mi' sv
+  double* sq = su + n;     // Mi r2
+  double* rowbuf = sq + n;
+  int* flag = reinterpret_cast<int*>(rowbuf + MN);
   if constexpr (link_tree_staged(MN)) {
-    // the four n x n operands of the products, staged in LDS by coalesced loads
+    // the four operands, staged in LDS by coalesced loads
     double* st = reinterpret_cast<double*>(flag + 4);
-    double *sGa = st, *sPsa = st + nn, *sP0b = st + 2 * nn, *sGb = st + 3 * nn;
-    load_block(sGa, n, Ga, n, n, n);
-    load_block(sPsa, n, Psa, n, n, n);
-    load_block(sP0b, n, P0b, n, n, n);
-    if (!exact_b) load_block(sGb, n, Gb, n, n, n);
+    double *sGa = st, *sPsa = st + blk, *sP0b = st + 2 * blk, *sGb = st + 3 * blk;
+    load_block(sGa, L, Ga, n, n, n);
+    load_block(sPsa, L, Psa, n, n, n);
+    load_block(sP0b, L, P0b, n, n, n);
+    if (!exact_b) load_block(sGb, L, Gb, n, n, n);
     Ga = sGa;
     Psa = sPsa;
     P0b = sP0b;
     Gb = sGb;
-    __syncthreads();
+    lg = L;
   }
-  if (threadIdx.x == 0) flag[0] = 0;
-  constexpr int E64 = fp64_engine(E);
-  pgemm_sub<E64, false, false, false, false>(n, n, n, P0b, n, Psa, n, 0, P0b, n, Psa, n,
-      [=](int i, int c, double v) { sN[c * mp + i] = v + (i == c ? 1.0 : 0.0); });
-  pgemm_sub<E64, false, true, false, false>(n, n, n, P0b, n, Ga, n, 0, P0b, n, Ga, n,
-      [=](int i, int c, double v) { sN[(n + c) * mp + i] = v; });
-  gemv2(n, n, P0b, n, psa, 0, psa, 0, psa, [=](int i, double v) { sN[2 * n * mp + i] = pb[i] + v; });
-  if (!exact_b)
-    for (int e = threadIdx.x; e < nn; e += kThreads) {
-      const int r = e / n, c = e - r * n;
-      sN[(2 * n + 1 + c) * mp + r] = Gb[e];
-    }
   __syncthreads();
-  gj_columns<MN>(sN, mp, n, nc, gjb, prow, flag);
+  constexpr int E64 = fp64_engine(E);
+  // M = I + P0_b Psi_a (column-major), R = P0_b Gam_a', r2, sv
+  pgemm_sub<E64, false, false, false, false>(n, n, n, P0b, lg, Psa, lg, 0, P0b, lg, Psa, lg,
+      [=](int i, int c, double v) { sM[c * L + i] = v + (i == c ? 1.0 : 0.0); });
+  pgemm_sub<E64, false, true, false, false>(n, n, n, P0b, lg, Ga, lg, 0, P0b, lg, Ga, lg,
+      [=](int i, int c, double v) { sR[i * L + c] = v; });
+  gemv2(n, n, P0b, lg, psa, 0, psa, 0, psa, [=](int i, double v) { r2[i] = pb[i] + v; });
+  if (!exact_b)
+    gemv2(n, n, Psa, lg, pb, 0, pb, 0, pb, [=](int i, double v) { sv[i] = psa[i] - v; });
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int bad = wave_invert<MN>(sM, L, n, sM, L, rowbuf);
+    if (threadIdx.x == 0) flag[0] = bad;
+  }
+  __syncthreads();
+  // Y = Gam_a Mi, V = Psi_a Mi, q = Mi r2, u = Mi' sv
+  pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, lg, sM, L, 0, Ga, lg, sM, L,
+      [=](int i, int c, double v) { sY[i * L + c] = v; });
+  if (!exact_b) {
+    pgemm_sub<E64, false, true, false, false>(n, n, n, Psa, lg, sM, L, 0, Psa, lg, sM, L,
+        [=](int i, int c, double v) { sV[i * L + c] = v; });
+    gemv2(n, n, sM, L, sv, 0, sv, 0, sv, [=](int i, double v) { su[i] = v; });
+  }
+  gemv_cm(n, n, sM, L, r2, [=](int i, double v) { sq[i] = v; });
+  __syncthreads();
   double* oP0 = o;
   double* oG = o + nn;
   double* oPs = o + 2 * nn;
   double* op = o + 3 * nn;
   double* ops = op + n;
-  pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, n, sN + n * mp, mp, 0, Ga, n, sN, mp,
+  // P0_ab = P0_a + Y R (lower half, mirrored), pbar_ab = pbar_a + Gam_a q
+  pgemm_sub<E64, false, false, false, false>(n, n, n, sY, L, sR, L, 0, sY, L, sR, L,
       [=](int i, int c, double v) {
         if (i >= c) {
           v += 0.5 * (P0a[i * n + c] + P0a[c * n + i]);
@@ -119,15 +143,18 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
         }
       },
       SkipUpper{n});
-  gemv2(n, n, Ga, n, sN + 2 * n * mp, 0, sv, 0, sv, [=](int i, double v) { op[i] = pa[i] + v; });
+  gemv2(n, n, Ga, lg, sq, 0, sq, 0, sq, [=](int i, double v) { op[i] = pa[i] + v; });
   if (!exact_b) {
-    pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, n, sN + (2 * n + 1) * mp, mp, 0, Ga, n, sN, mp,
+    // Gam_ab = Y Gam_b, U = V Gam_b (into sM: Mi is no longer read),
+    // psi_ab = psi_b + Gam_b' u
+    pgemm_sub<E64, false, false, false, false>(n, n, n, sY, L, Gb, lg, 0, sY, L, Gb, lg,
         [=](int i, int c, double v) { oG[i * n + c] = v; });
-    pgemm_sub<E64, false, false, false, false>(n, n, n, Psa, n, Gb, n, 0, Psa, n, Gb, n,
-        [=](int i, int c, double v) { sW[i * n + c] = v; });
-    gemv2(n, n, Psa, n, pb, 0, pb, 0, pb, [=](int i, double v) { sv[i] = psa[i] - v; });
+    pgemm_sub<E64, false, false, false, false>(n, n, n, sV, L, Gb, lg, 0, sV, L, Gb, lg,
+        [=](int i, int c, double v) { sM[i * L + c] = v; });
+    gemv_cm(n, n, Gb, lg, su, [=](int i, double v) { ops[i] = psb[i] + v; });
     __syncthreads();
-    pgemm_sub<E64, false, false, false, false>(n, n, n, sN + (2 * n + 1) * mp, mp, sW, n, 0, sW, n, sW, n,
+    // Psi_ab = Psi_b + Gam_b' U (lower half, mirrored)
+    pgemm_sub<E64, true, false, false, false>(n, n, n, Gb, lg, sM, L, 0, Gb, lg, sM, L,
         [=](int i, int c, double v) {
           if (i >= c) {
             v += 0.5 * (Psb[i * n + c] + Psb[c * n + i]);
@@ -136,10 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
           }
         },
         SkipUpper{n});
-    gemv2(n, n, sN + (2 * n + 1) * mp, mp, sv, 0, sv, 0, sv,
-          [=](int i, double v) { ops[i] = psb[i] + v; });
   }
-  __syncthreads();
   if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
 }
 
@@ -150,7 +174,7 @@ template <int MN, int E>
 __global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double* fin) {
   extern __shared__ double smem[];
   const int n = d.n, J = d.J, j = blockIdx.x;
-  const int nn = n * n;
+  const int nn = n * n, L = ld_odd(n), blk = n * L;
   {
     const double* s = scan_elem(const_cast<double*>(fin), n, j);
     double* bnd = ws_bnd(d.ws, n, J, j);
@@ -163,31 +187,27 @@ __global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double
   const double* pn = nx + 3 * nn;
   const double* sg = ws_seg(d.ws, n, j);
   const double *Gam = sg + nn, *Psi = sg + 2 * nn, *psi = sg + 3 * nn + n;
-  const int mp = MN + 1;
-  double* sN = smem;  // mp x (2n+1) column-major: [N | Gam' | w] -> [. | F | f]
-  double* gjb = sN + mp * (2 * n + 1);
-  int* prow = reinterpret_cast<int*>(gjb + 3 * MN + 2);
-  int* flag = prow + MN;
-  if (threadIdx.x == 0) flag[0] = 0;
+  double* sN = smem;        // N, column-major -> its inverse in place
+  double* sG = sN + blk;    // Gam (row-major)
+  double* sw = sG + blk;    // psi - Psi pn
+  double* rowbuf = sw + n;
+  int* flag = reinterpret_cast<int*>(rowbuf + MN);
   constexpr int E64 = fp64_engine(E);
+  load_block(sG, L, Gam, n, n, n);
   pgemm_sub<E64, false, false, false, false>(n, n, n, Psi, n, Pn, n, 0, Psi, n, Pn, n,
-      [=](int i, int c, double v) { sN[c * mp + i] = v + (i == c ? 1.0 : 0.0); });
-  for (int e = threadIdx.x; e < nn; e += kThreads) {
-    const int r = e / n, i = e - r * n;
-    sN[(n + r) * mp + i] = Gam[e];
-  }
-  gemv2(n, n, Psi, n, pn, 0, pn, 0, pn, [=](int i, double v) { sN[2 * n * mp + i] = psi[i] - v; });
+      [=](int i, int c, double v) { sN[c * L + i] = v + (i == c ? 1.0 : 0.0); });
+  gemv2(n, n, Psi, n, pn, 0, pn, 0, pn, [=](int i, double v) { sw[i] = psi[i] - v; });
   __syncthreads();
-  gj_columns<MN>(sN, mp, n, 2 * n + 1, gjb, prow, flag);
-  double* lk = ws_link(d.ws, n, J, j);
-  for (int e = threadIdx.x; e < n * (n + 1); e += kThreads) {
-    const int c = e / n, r = e - c * n;
-    const double v = sN[(n + c) * mp + r];
-    if (c < n)
-      lk[r * n + c] = v;
-    else
-      lk[nn + r] = v;
+  if (threadIdx.x < 64) {
+    const int bad = wave_invert<MN>(sN, L, n, sN, L, rowbuf);
+    if (threadIdx.x == 0) flag[0] = bad;
   }
+  __syncthreads();
+  double* lk = ws_link(d.ws, n, J, j);
+  // F = N^{-1} Gam' (row-major to the workspace), f = N^{-1} w
+  pgemm_sub<E64, true, true, false, false>(n, n, n, sN, L, sG, L, 0, sN, L, sG, L,
+      [=](int i, int c, double v) { lk[i * n + c] = v; });
+  gemv_cm(n, n, sN, L, sw, [=](int i, double v) { lk[nn + i] = v; });
   if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
 }
 

@@ -641,36 +641,37 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
 }
 
 // Linking solve. With (Pn, pn) the exact value at t_{j+1} and N = I + Psi_j Pn:
-//   [F | f] = N^{-1} [Gam_j' | psi_j - Psi_j pn]       (Gauss-Jordan, row pivoting)
+//   [F | f] = N^{-1} [Gam_j' | psi_j - Psi_j pn]   (explicit inverse, one wave)
 //   P_{t_j} = P0_j + Gam_j Pn F,   p_{t_j} = pbar_j + Gam_j (pn + Pn f)
 // which is the elimination of x_{t_{j+1}} and the link multiplier
 // mu_j = (I + Pn Psi_j)^{-1}(Pn (Gam_j' x + psi_j) + pn) from the segment's
-// value; forward, x_{t_{j+1}} = F x_{t_j} + f.
+// value; forward, x_{t_{j+1}} = F x_{t_j} + f. Blocks in LDS are
+// n x ld_odd(n), row-major unless noted.
 template <int MN, int E>
 LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   const int n = d.n, J = d.J;
-  const int mp = MN + 1, MX = MN;
-  double* sPn = smem;                 // n x n row-major
-  double* spn = sPn + n * n;
-  double* sA1 = spn + n;              // n x n row-major: Psi, then Gam
-  double* sN = sA1 + n * n;           // mp x (2n+1) column-major: [N | Gam' | w] -> [T1 | F | f]
-  double* sv = sN + mp * (2 * n + 1);
-  double* sx = sv + n;
+  const int L = ld_odd(n), blk = n * L;
+  double* sPn = smem;        // exact value at t_{j+1}
+  double* sA1 = sPn + blk;   // Psi, then Gam
+  double* sN = sA1 + blk;    // N, column-major -> its inverse in place -> T1 = Pn F
+  double* sF = sN + blk;     // F
+  double* spn = sF + blk;
+  double* sv = spn + n;      // w = psi - Psi pn, then pn + Pn f
+  double* sf = sv + n;
+  double* sx = sf + n;
   double* sxn = sx + n;
-  double* gjb = sxn + n;              // Gauss-Jordan exchange: 3 * MX + 2
-  int* prow = reinterpret_cast<int*>(gjb + 3 * MX + 2);
-  int* flag = prow + MX;
+  double* rowbuf = sxn + n;
+  int* flag = reinterpret_cast<int*>(rowbuf + MN);
 
   if (threadIdx.x == 0) {
     int f = 0;
     for (int j = 0; j < J; ++j) f = combine_info(f, d.fail[j]);
     flag[0] = f;  // stage failure (or non-finite value) from phase 1
     flag[1] = 0;  // linking failure
-    flag[2] = 0;  // pivot flag of the current boundary
   }
   {
     const double* bl = ws_bnd(d.ws, n, J, J - 1);
-    load_block(sPn, n, bl, n, n, n);
+    load_block(sPn, L, bl, n, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) spn[i] = bl[n * n + i];
   }
   for (int j = J - 2; j >= 0; --j) {
@@ -680,52 +681,51 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
     const double* Psi = sg + 2 * n * n;
     const double* pbar = sg + 3 * n * n;
     const double* psi = pbar + n;
-    load_block(sA1, n, Psi, n, n, n);
-    // Gam' into columns [n, 2n) of sN: column n + r holds row r of Gam
-    for (int e = threadIdx.x; e < n * n; e += kThreads) {
-      const int r = e / n, i = e - r * n;
-      sN[(n + r) * mp + i] = Gam[e];
-    }
+    load_block(sA1, L, Psi, n, n, n);
     __syncthreads();
-    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, n, sPn, n, 0, sA1, n, sPn, n,
+    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sPn, L, 0, sA1, L, sPn, L,
                                           [=](int i, int jj, double v) {
-                                            sN[jj * mp + i] = v + (i == jj ? 1.0 : 0.0);
+                                            sN[jj * L + i] = v + (i == jj ? 1.0 : 0.0);
                                           });
-    gemv2(n, n, sA1, n, spn, 0, spn, 0, spn,
-          [=](int i, double v) { sN[2 * n * mp + i] = psi[i] - v; });
+    gemv2(n, n, sA1, L, spn, 0, spn, 0, spn, [=](int i, double v) { sv[i] = psi[i] - v; });
     __syncthreads();
-    load_block(sA1, n, Gam, n, n, n);  // Psi no longer needed
-    gj_columns<MN>(sN, mp, n, 2 * n + 1, gjb, prow, flag + 2);
-    {  // [F | f] to the workspace for the forward pass
-      double* lk = ws_link(d.ws, n, J, j);
-      for (int e = threadIdx.x; e < n * (n + 1); e += kThreads) {
-        const int c = e / n, r = e - c * n;  // column c of [F | f], row r
-        const double v = sN[(n + c) * mp + r];
-        if (c < n)
-          lk[r * n + c] = v;
-        else
-          lk[n * n + r] = v;
-      }
+    load_block(sA1, L, Gam, n, n, n);  // Psi no longer needed
+    if (threadIdx.x < 64) {
+      const int bad = wave_invert<MN>(sN, L, n, sN, L, rowbuf);
+      if (threadIdx.x == 0 && bad && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
     }
-    // T1 = Pn F -> sN columns [0, n) ;  v = pn + Pn f
-    pgemm_sub<fp64_engine(E), false, true, false, false>(n, n, n, sPn, n, sN + n * mp, mp, 0, sPn, n, sN, mp,
-                                         [=](int i, int jj, double v) { sN[jj * mp + i] = v; });
-    gemv2(n, n, sPn, n, sN + 2 * n * mp, 0, spn, 0, spn, [=](int i, double v) { sv[i] = spn[i] + v; });
     __syncthreads();
-    pgemm_sub<fp64_engine(E), false, true, false, false>(n, n, n, sA1, n, sN, mp, 0, sA1, n, sN, mp,
+    // [F | f] = N^{-1} [Gam' | w], kept in LDS and written to the workspace
+    // for the forward pass
+    double* lk = ws_link(d.ws, n, J, j);
+    pgemm_sub<fp64_engine(E), true, true, false, false>(n, n, n, sN, L, sA1, L, 0, sN, L, sA1, L,
+        [=](int i, int jj, double v) {
+          sF[i * L + jj] = v;
+          lk[i * n + jj] = v;
+        });
+    gemv_cm(n, n, sN, L, sv, [=](int i, double v) {
+      sf[i] = v;
+      lk[n * n + i] = v;
+    });
+    __syncthreads();
+    // T1 = Pn F -> sN ;  v = pn + Pn f
+    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sPn, L, sF, L, 0, sPn, L, sF, L,
+                                         [=](int i, int jj, double v) { sN[i * L + jj] = v; });
+    gemv2(n, n, sPn, L, sf, 0, spn, 0, spn, [=](int i, double v) { sv[i] = spn[i] + v; });
+    __syncthreads();
+    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sN, L, 0, sA1, L, sN, L,
         [=](int i, int jj, double v) {
           if (i >= jj) {
             v += 0.5 * (P0[i * n + jj] + P0[jj * n + i]);
-            sPn[i * n + jj] = v;
-            sPn[jj * n + i] = v;
+            sPn[i * L + jj] = v;
+            sPn[jj * L + i] = v;
           }
         },
         SkipUpper{n});
-    gemv2(n, n, sA1, n, sv, 0, sv, 0, sv, [=](int i, double v) { spn[i] = pbar[i] + v; });
+    gemv2(n, n, sA1, L, sv, 0, sv, 0, sv, [=](int i, double v) { spn[i] = pbar[i] + v; });
     __syncthreads();
-    if (threadIdx.x == 0 && flag[2] && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
     double* b = ws_bnd(d.ws, n, J, j);
-    store_block(b, n, sPn, n, n, n);
+    store_block(b, n, sPn, L, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = spn[i];
   }
   // forward over the boundaries: x_{t_0} = x0, x_{t_{j+1}} = F_j x_{t_j} + f_j

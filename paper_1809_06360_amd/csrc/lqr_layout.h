@@ -203,26 +203,28 @@ LQR_HD size_t dual_lds(int n, int m, int mw) {
 // Problems with at least this many states run their products on matrix cores.
 constexpr int kMfmaMinN = 32;
 
-// Linking solve: sPn n x n, spn n, sA1 n x n, sN mp x (2n+1) column-major
-// (mp = pad_rows(n) + 1), vectors, Gauss-Jordan exchange (3 pad + 2), pivots.
+// LDS of the serial linking solve (defined below).
 LQR_HD size_t couple_lds(int n, int nw);
 
 // Register width of the linking solve inside the persistent kernel: one
 // width per product engine (MFMA variants serve n <= 64, VALU ones n < 32).
 LQR_HD constexpr int persist_nw(bool mf) { return mf ? 64 : 32; }
 
-// Join of two summaries: [M | RHS] mp x (3n+1) column-major, Psi_a Gam_b
-// (n x n), a vector, Gauss-Jordan exchange and pivots (the link-map kernel
-// uses less).
-// Up to this register width the join also stages its four n x n product
-// operands in LDS (they fit next to the elimination block).
+// Leading dimension of an n x n block in LDS: odd, so that the 16 lanes of a
+// matrix-core operand fragment that walk a strided row or column of the block
+// hit distinct LDS banks.
+LQR_HD constexpr int ld_odd(int n) { return n | 1; }
+
+// Join of two summaries: the four n x n operands staged in LDS (register
+// widths up to 48; wider joins read them from global memory), four n x n
+// work blocks (M and its inverse, the right-hand side, and two products of
+// the inverse), four vectors, the inversion's row buffer and a flag word.
 LQR_HD constexpr bool link_tree_staged(int nw) { return nw <= 48; }
 
 LQR_HD size_t link_tree_lds(int n, int nw) {
-  const size_t mx = (size_t)nw, mp = mx + 1;
-  size_t dbl = mp * (3 * (size_t)n + 1) + (size_t)n * n + n + 3 * mx + 2;
-  if (link_tree_staged(nw)) dbl += 4 * (size_t)n * n + 1;
-  return dbl * 8 + (mx + 4) * 4 + 64;
+  const size_t blk = (size_t)n * ld_odd(n);
+  const size_t dbl = (link_tree_staged(nw) ? 8 : 4) * blk + 4 * (size_t)n + (size_t)nw + 2;
+  return dbl * 8 + 64;
 }
 
 // ---------------------------------------------------------------------------
@@ -270,10 +272,11 @@ LQR_HD size_t big_link_lds() { return kBigPanelBytes + (512 + 4 * 128) * 8 + 256
 LQR_HD size_t rollout_lds(int /*n*/, int /*m*/) { return (4 * 128 + 4 * 64) * 8 + 64; }
 
 // `nw` is the register width of the kernel variant (pad_rows of the largest n).
+// Four n x n blocks (exact value, Psi then Gam, N then its inverse, F), five
+// vectors, the inversion's row buffer and three flag words.
 LQR_HD size_t couple_lds(int n, int nw) {
-  const size_t mx = (size_t)nw, mp = mx + 1;
-  const size_t dbl = 2 * (size_t)n * n + 4 * (size_t)n + mp * (2 * n + 1) + 3 * mx + 2;
-  return dbl * 8 + (mx + 4) * 4 + 64;
+  const size_t dbl = 4 * (size_t)n * ld_odd(n) + 5 * (size_t)n + (size_t)nw;
+  return dbl * 8 + 4 * 4 + 64;
 }
 
 }  // namespace lqr

@@ -208,6 +208,24 @@ LQR_DEV void gemv2(int rows, int c1, const T* M1, int ld1, const T* v1,
   }
 }
 
+// y(i) = epi(i, sum_l A[l * lda + i] v[l]) for i < rows <= kThreads: a
+// column-major A (or the transpose of a row-major block); thread i walks row i
+// with two accumulation chains.
+template <typename T, typename Epi>
+LQR_DEV void gemv_cm(int rows, int cols, const T* A, int lda, const T* v, Epi epi) {
+  const int i = threadIdx.x;
+  if (i < rows) {
+    T s0 = T(0), s1 = T(0);
+    int l = 0;
+    for (; l + 1 < cols; l += 2) {
+      s0 = fma(A[l * lda + i], v[l], s0);
+      s1 = fma(A[(l + 1) * lda + i], v[l + 1], s1);
+    }
+    if (l < cols) s0 = fma(A[l * lda + i], v[l], s0);
+    epi(i, s0 + s1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Cross-lane helpers.
 // ---------------------------------------------------------------------------
@@ -399,106 +417,127 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
 }
 
 // ---------------------------------------------------------------------------
-// Gauss-Jordan elimination with row pivoting of an n x nc column-major block
-// (n <= MAXN <= 64 rows, nc <= 256 columns, leading dimension ldg, in LDS):
-// columns [0, n) hold the square matrix N, the rest are right-hand sides.
-// Thread c owns column c in registers (rows n..MAXN-1 are zero padding). In
-// round k the owner of column k publishes it to a double-buffered LDS vector;
-// every wave then finds the pivot row p (largest magnitude among the rows not
-// yet used) by a wave reduction, and every column c > k eliminates column k
-// from all rows but p. After n rounds
-// the solution row k of N^{-1} X is (row p_k of the right-hand sides) /
-// pivot_k; it is written back to G's rows in natural order (columns [n, nc)),
-// so G[:, n:nc) <- N^{-1} G[:, n:nc). A zero or non-finite pivot is replaced by
-// NaN and *bad is set to 1. buf: 3 * MAXN doubles and MAXN ints of LDS
-// (exchange, pivots, rows). n <= 64 (one row per lane in the pivot search). Requires a barrier between G's producer and this call; ends
-// with a barrier.
+// Inverse of an n x n matrix (n <= MAXN <= 64) by ONE wave, with no workgroup
+// barrier: Gauss-Jordan exchange steps with row pivoting. Lane i keeps row i
+// of the working table in registers; step k pivots column k on the unused row
+// p of largest magnitude (a max-reduction over lanes), lane p hands its row to
+// the wave through `rowbuf` (LDS, ordered by the wave's own in-order LDS
+// queue) and every other row i takes
+//   a(i, j) -= a(i, k)/a(p, k) * a(p, j)  (j != k),   a(i, k) /= a(p, k).
+// The exchange would also scale the pivot row by -1/a(p, k); that scale is
+// kept aside per lane (sigma) and applied once at the end, so a step costs
+// one fused multiply-add per element on every lane alike (later steps treat
+// the stored row exactly, since the scale cancels from their updates). After
+// n steps lane i holds row step(i) of the inverse with its columns in pivot
+// order: inverse(step(i), p_k) = sigma_i * a(i, k).
+// Input element (i, j) at A[j * lda + i]; the inverse goes to Ainv with the
+// same column-major convention (Ainv may be A: all of A is read before any
+// write). A zero or non-finite pivot yields NaN results and returns 1.
+// Called by the 64 lanes of one wave together; the caller orders the producer
+// of A and the consumers of Ainv with workgroup barriers.
 // ---------------------------------------------------------------------------
-// v[p] for a wave-uniform index p (binary search over scalar branches).
-template <int LO, int HI, int MAXN>
-LQR_DEV double pick(const double (&v)[MAXN], int p) {
-  if constexpr (HI - LO == 1) {
-    return v[LO];
-  } else {
-    constexpr int MID = (LO + HI) / 2;
-    return p < MID ? pick<LO, MID, MAXN>(v, p) : pick<MID, HI, MAXN>(v, p);
+// Largest unsigned value over the wave (all 64 lanes active).
+LQR_DEV unsigned wave_max_u32(unsigned v) {
+  unsigned o;
+  o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v = v > o ? v : o;
+  o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v = v > o ? v : o;
+  o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v = v > o ? v : o;
+  o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v = v > o ? v : o;
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  const unsigned s0 = r0 > r1 ? r0 : r1, s1 = r2 > r3 ? r2 : r3;
+  return s0 > s1 ? s0 : s1;
+}
+
+// Compile-time loop: f(Int<I>{}) for I in [B, E), so that register arrays
+// indexed by the loop variable stay in registers however long the body is.
+template <int V>
+struct Int {
+  static constexpr int value = V;
+};
+template <int B, int E, typename F>
+LQR_DEV void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(Int<B>{});
+    static_for<B + 1, E>(f);
   }
 }
 
 template <int MAXN>
-LQR_DEV void gj_columns(double* G, int ldg, int n, int nc, double* buf, int* prow, int* bad) {
-  const int c = threadIdx.x;
+LQR_DEV int wave_invert(const double* A, int lda, int n, double* Ainv, int ldi, double* rowbuf) {
+  static_assert(MAXN <= 64, "one row per lane");
   const int lane = threadIdx.x & 63;
-  const bool own = c < nc;
-  double* pivs = buf + 2 * MAXN;  // MAXN pivot values
-  double v[MAXN];
-  const double* src = G + (own ? c : 0) * ldg;
+  const bool live = lane < n;
+  // Rows past n (lanes that never pivot) and columns past n are padding: they
+  // load clamped copies and are never read back into the first n columns.
+  const int row = live ? lane : 0;
+  double a[MAXN];
 #pragma unroll
-  for (int i = 0; i < MAXN; ++i) {
-    const double g = src[i];
-    v[i] = (own && i < n) ? g : 0.0;
-  }
-  unsigned long long used = 0ull;
+  for (int j = 0; j < MAXN; ++j) a[j] = A[(j < n ? j : n - 1) * lda + row];
+  bool used = !live;
+  int step = 0, prow = 0, bad = 0;
+  double sigma = 1.0;
+  static_for<0, MAXN>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (k < n) {
+      // pivot: largest |a(i, k)| over unused rows. Key = high word of |a|
+      // (exponent and leading mantissa bits) with its low 6 bits replaced by
+      // 63 - lane (ties go to the lowest row), offset so that any unused row
+      // outranks the used ones; NaN and infinity rank first.
+      const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, a[k]) >> 32) & 0x7fffffffu;
+      const unsigned key = wave_max_u32(used ? 0u : ((hi & ~63u) | (unsigned)(63 - lane)) + 64u);
+      const int p = 63 - (int)(key & 63u);
+      double piv = readlane(a[k], p);
+      if (!(piv != 0.0) || !isfinite(piv)) {
+        bad = 1;
+        piv = qnan<double>();
+      }
+      const double inv = 1.0 / piv;
+      const bool isp = lane == p;
+      // the previous step's reads of rowbuf precede this store, and the store
+      // precedes this step's reads (LDS is in order within a wave; the fences
+      // keep the compiler from moving the accesses across lanes' boundaries)
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (isp) {
+#pragma unroll
+        for (int j = 0; j < MAXN; ++j) rowbuf[j] = a[j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // the whole pivot row is requested before the first use
+      double r[MAXN];
+#pragma unroll
+      for (int j = 0; j < MAXN; ++j) r[j] = rowbuf[j];
+      __builtin_amdgcn_sched_barrier(0);
+      const double g = a[k] * inv;
+      const double c = isp ? 0.0 : -g;
+#pragma unroll
+      for (int j = 0; j < MAXN; ++j)
+        if (j != k) a[j] = fma(c, r[j], a[j]);
+      a[k] = isp ? -1.0 : g;
+      if (isp) {
+        sigma = -inv;
+        used = true;
+        step = k;
+      }
+      if (lane == k) prow = p;
+    }
+  });
 #pragma unroll
   for (int k = 0; k < MAXN; ++k) {
     if (k < n) {
-      double* cb = buf + (k & 1) * MAXN;
-      if (c == k) {
-#pragma unroll
-        for (int i = 0; i < MAXN; ++i) cb[i] = v[i];
-      }
-      __syncthreads();
-      // the published column, loaded up front (broadcast reads)
-      double mk[MAXN];
-#pragma unroll
-      for (int i = 0; i < MAXN; ++i) mk[i] = cb[i];
-      // pivot: argmax |column k| over unused rows, by every wave (lane = row).
-      // Key = bits of |value| with the low 6 mantissa bits replaced by
-      // (63 - row): non-negative doubles order like their bit patterns, ties
-      // go to the lowest row, NaN and inf sort first.
-      long long key = -1;
-      if (lane < n && !((used >> lane) & 1ull)) {
-        double a = fabs(cb[lane]);
-        if (!(a <= 1.7976931348623157e308)) a = __builtin_inf();
-        key = (long long)((__builtin_bit_cast(unsigned long long, a) & ~63ull) | (unsigned)(63 - lane));
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const long long o = __shfl_xor(key, off, 64);
-        key = o > key ? o : key;
-      }
-      const int p = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63));
-      double dp = cb[p];
-      if (!(dp != 0.0) || !isfinite(dp)) {
-        dp = qnan<double>();
-        if (c == k) *bad = 1;
-      }
-      if (c == k) {
-        pivs[k] = dp;
-        prow[k] = p;
-      }
-      used |= 1ull << p;
-      if (own && c > k) {
-        const double rp = pick<0, MAXN, MAXN>(v, p) / dp;
-#pragma unroll
-        for (int i = 0; i < MAXN; ++i) v[i] = (i == p) ? v[i] : fma(-mk[i], rp, v[i]);
-      }
+      const int col = __builtin_amdgcn_readlane(prow, k);
+      if (live) Ainv[col * ldi + step] = sigma * a[k];
     }
   }
-  __syncthreads();
-  if (own && c >= n) {  // un-permute: solution row k is row prow[k] / pivot k
-    double* col = G + c * ldg;
-#pragma unroll
-    for (int i = 0; i < MAXN; ++i)
-      if (i < n) col[i] = v[i];
-#pragma unroll
-    for (int k = 0; k < MAXN; ++k)
-      if (k < n) v[k] = col[prow[k]] / pivs[k];
-#pragma unroll
-    for (int k = 0; k < MAXN; ++k)
-      if (k < n) col[k] = v[k];
-  }
-  __syncthreads();
+  return bad;
 }
 
 // ---------------------------------------------------------------------------

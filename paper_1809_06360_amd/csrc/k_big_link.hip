@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBT) void k_big_link_maps(InstDesc d, const double*
   __syncthreads();
   big::gj_invert(E, ld, n, s.xb, s.rowof, s.flag);
   double* lk = ws_link(d.ws, n, J, j);
-  bmm1<1, false, true, kBT>(n, n, n, E, ld, Gam, n, [=](int i, int c, double v) { lk[i * n + c] = v; });
+  bmm1<1, false, true, kBT>(n, n, n, E, ld, Gam, n, [=](int i, int c, double v) { lk[c * n + i] = v; });
   bgemv(n, n, E, ld, w, [=](int i, double v) { lk[nn + i] = v; });
   __syncthreads();
   if (threadIdx.x == 0 && *s.flag) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
@@ -153,7 +153,8 @@ __global__ __launch_bounds__(kBT) void k_big_link_maps(InstDesc d, const double*
 
 // Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, then the
 // instance's info word. Thread t keeps a quarter row of F_j in registers
-// (row t/4, columns 32 (t%4) ..) and loads that of F_{j+1} while step j runs.
+// (row t/4, columns 32 (t%4) ..) and loads that of F_{j+1} while step j runs;
+// F is column-major, so 16 consecutive rows of a column are one load.
 __global__ __launch_bounds__(kBT) void k_big_link_forward(InstDesc d) {
   extern __shared__ double smem[];
   const int n = d.n, J = d.J, nn = n * n;
@@ -167,9 +168,9 @@ __global__ __launch_bounds__(kBT) void k_big_link_forward(InstDesc d) {
   auto fetch = [&](double (&dst)[32], int jj) {
     const double* F = ws_link(d.ws, n, J, jj);
     const bool ok = r < n;
-    const double* row = F + (size_t)(ok ? r : 0) * n;
+    const double* row = F + (ok ? r : 0);
 #pragma unroll
-    for (int c = 0; c < 32; ++c) dst[c] = (ok && c0 + c < n) ? row[c0 + c] : 0.0;
+    for (int c = 0; c < 32; ++c) dst[c] = (ok && c0 + c < n) ? row[(size_t)(c0 + c) * n] : 0.0;
   };
   if (J > 1) fetch(cur, 0);
   __syncthreads();

@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kThreads) void k_link_init(InstDesc d) {
 
 // One scan round: out[j] = in[j] (x) in[j + dist], or in[j] when j + dist >= J
 // (then in[j] already reaches the last segment and only its P0, pbar are used).
-// The join works from the explicit inverse Mi = M^{-1} (one wave, see
-// wave_invert) and the identities X1 = Mi P0_b Gam_a', X3 = Mi Gam_b and
+// The join works from the explicit inverse Mi = M^{-1} (see wg_invert) and
+// the identities X1 = Mi P0_b Gam_a', X3 = Mi Gam_b and
 // Mi' Psi_a = Psi_a Mi (so V = Psi_a Mi is symmetric):
 //   P0_ab  = P0_a + Y R,      Y = Gam_a Mi,  R = P0_b Gam_a'
 //   pbar_ab = pbar_a + Gam_a Mi (P0_b psi_a + pbar_b)
@@ -86,11 +86,10 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
   double* sv = r2 + n;     // psi_a - Psi_a pbar_b
   double* su = sv + n;     // Mi' sv
   double* sq = su + n;     // Mi r2
-  double* rowbuf = sq + n;
-  int* flag = reinterpret_cast<int*>(rowbuf + MN);
+  const InvExchange ix = carve_inv_exchange(sq + n);
   if constexpr (link_tree_staged(MN)) {
     // the four operands, staged in LDS by coalesced loads
-    double* st = reinterpret_cast<double*>(flag + 4);
+    double* st = sq + n + kInvExchangeDoubles;
     double *sGa = st, *sPsa = st + blk, *sP0b = st + 2 * blk, *sGb = st + 3 * blk;
     load_block(sGa, L, Ga, n, n, n);
     load_block(sPsa, L, Psa, n, n, n);
@@ -109,24 +108,20 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
       [=](int i, int c, double v) { sM[c * L + i] = v + (i == c ? 1.0 : 0.0); });
   pgemm_sub<E64, false, true, false, false>(n, n, n, P0b, lg, Ga, lg, 0, P0b, lg, Ga, lg,
       [=](int i, int c, double v) { sR[i * L + c] = v; });
-  gemv2(n, n, P0b, lg, psa, 0, psa, 0, psa, [=](int i, double v) { r2[i] = pb[i] + v; });
+  // P0_b and Psi_a are symmetric: their products walk coalesced columns
+  gemv_cm_wave(1, n, n, P0b, lg, psa, [=](int i, double v) { r2[i] = pb[i] + v; });
   if (!exact_b)
-    gemv2(n, n, Psa, lg, pb, 0, pb, 0, pb, [=](int i, double v) { sv[i] = psa[i] - v; });
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int bad = wave_invert<MN>(sM, L, n, sM, L, rowbuf);
-    if (threadIdx.x == 0) flag[0] = bad;
-  }
-  __syncthreads();
+    gemv_cm_wave(2, n, n, Psa, lg, pb, [=](int i, double v) { sv[i] = psa[i] - v; });
+  const int bad = wg_invert<MN>(sM, L, n, sM, L, ix);
   // Y = Gam_a Mi, V = Psi_a Mi, q = Mi r2, u = Mi' sv
   pgemm_sub<E64, false, true, false, false>(n, n, n, Ga, lg, sM, L, 0, Ga, lg, sM, L,
       [=](int i, int c, double v) { sY[i * L + c] = v; });
   if (!exact_b) {
     pgemm_sub<E64, false, true, false, false>(n, n, n, Psa, lg, sM, L, 0, Psa, lg, sM, L,
         [=](int i, int c, double v) { sV[i * L + c] = v; });
-    gemv2(n, n, sM, L, sv, 0, sv, 0, sv, [=](int i, double v) { su[i] = v; });
+    gemv_wave(1, n, n, sM, L, sv, [=](int i, double v) { su[i] = v; });
   }
-  gemv_cm(n, n, sM, L, r2, [=](int i, double v) { sq[i] = v; });
+  gemv_cm_wave(2, n, n, sM, L, r2, [=](int i, double v) { sq[i] = v; });
   __syncthreads();
   double* oP0 = o;
   double* oG = o + nn;
@@ -143,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
         }
       },
       SkipUpper{n});
-  gemv2(n, n, Ga, lg, sq, 0, sq, 0, sq, [=](int i, double v) { op[i] = pa[i] + v; });
+  gemv_wave(1, n, n, Ga, lg, sq, [=](int i, double v) { op[i] = pa[i] + v; });
   if (!exact_b) {
     // Gam_ab = Y Gam_b, U = V Gam_b (into sM: Mi is no longer read),
     // psi_ab = psi_b + Gam_b' u
@@ -151,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
         [=](int i, int c, double v) { oG[i * n + c] = v; });
     pgemm_sub<E64, false, false, false, false>(n, n, n, sV, L, Gb, lg, 0, sV, L, Gb, lg,
         [=](int i, int c, double v) { sM[i * L + c] = v; });
-    gemv_cm(n, n, Gb, lg, su, [=](int i, double v) { ops[i] = psb[i] + v; });
+    gemv_cm_wave(2, n, n, Gb, lg, su, [=](int i, double v) { ops[i] = psb[i] + v; });
     __syncthreads();
     // Psi_ab = Psi_b + Gam_b' U (lower half, mirrored)
     pgemm_sub<E64, true, false, false, false>(n, n, n, Gb, lg, sM, L, 0, Gb, lg, sM, L,
@@ -164,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
         },
         SkipUpper{n});
   }
-  if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
+  if (threadIdx.x == 0 && bad) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
 }
 
 // Boundary values from the scan result, and the link maps
@@ -190,32 +185,29 @@ __global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double
   double* sN = smem;        // N, column-major -> its inverse in place
   double* sG = sN + blk;    // Gam (row-major)
   double* sw = sG + blk;    // psi - Psi pn
-  double* rowbuf = sw + n;
-  int* flag = reinterpret_cast<int*>(rowbuf + MN);
+  const InvExchange ix = carve_inv_exchange(sw + n);
   constexpr int E64 = fp64_engine(E);
   load_block(sG, L, Gam, n, n, n);
   pgemm_sub<E64, false, false, false, false>(n, n, n, Psi, n, Pn, n, 0, Psi, n, Pn, n,
       [=](int i, int c, double v) { sN[c * L + i] = v + (i == c ? 1.0 : 0.0); });
-  gemv2(n, n, Psi, n, pn, 0, pn, 0, pn, [=](int i, double v) { sw[i] = psi[i] - v; });
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int bad = wave_invert<MN>(sN, L, n, sN, L, rowbuf);
-    if (threadIdx.x == 0) flag[0] = bad;
-  }
-  __syncthreads();
+  // Psi is symmetric: its product walks coalesced columns
+  gemv_cm_wave(1, n, n, Psi, n, pn, [=](int i, double v) { sw[i] = psi[i] - v; });
+  const int bad = wg_invert<MN>(sN, L, n, sN, L, ix);
   double* lk = ws_link(d.ws, n, J, j);
-  // F = N^{-1} Gam' (row-major to the workspace), f = N^{-1} w
-  pgemm_sub<E64, true, true, false, false>(n, n, n, sN, L, sG, L, 0, sN, L, sG, L,
-      [=](int i, int c, double v) { lk[i * n + c] = v; });
-  gemv_cm(n, n, sN, L, sw, [=](int i, double v) { lk[nn + i] = v; });
-  if (threadIdx.x == 0 && flag[0]) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
+  // F' = Gam N^{-T} (row c of F' is column c of F: the workspace keeps F
+  // column-major, with coalesced stores here), f = N^{-1} w
+  pgemm_sub<E64, false, false, false, false>(n, n, n, sG, L, sN, L, 0, sG, L, sN, L,
+      [=](int c, int i, double v) { lk[c * n + i] = v; });
+  gemv_cm_wave(1, n, n, sN, L, sw, [=](int i, double v) { lk[nn + i] = v; });
+  if (threadIdx.x == 0 && bad) atomicMax(d.fail + J, LQR_INFO_COUPLING + j);
 }
 
 // Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, and the
 // instance's info word (a stage failure of phase 1 takes precedence). The
 // chain is serial and latency-bound, so it runs in one wave: lane i keeps row
-// i of F_j in registers (row i of F_{j+1} is loaded while step j computes)
-// and the state vector is exchanged through LDS with wave-level ordering.
+// i of F_j in registers (row i of F_{j+1} is loaded while step j computes;
+// with F column-major each of those loads is one coalesced column) and the
+// state vector is exchanged through LDS with wave-level ordering.
 template <int MN>
 __global__ __launch_bounds__(64) void k_link_forward(InstDesc d) {
   extern __shared__ double smem[];
@@ -233,27 +225,29 @@ __global__ __launch_bounds__(64) void k_link_forward(InstDesc d) {
 #pragma unroll
   for (int k = 0; k < MN; ++k) cur[k] = 0.0;
   if (J > 1 && row) {
-    const double* F = ws_link(d.ws, n, J, 0) + lane * n;
+    const double* F = ws_link(d.ws, n, J, 0) + lane;
 #pragma unroll
-    for (int k = 0; k < MN; ++k) cur[k] = k < n ? F[k] : 0.0;
+    for (int k = 0; k < MN; ++k) cur[k] = k < n ? F[k * n] : 0.0;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   for (int j = 0; j < J - 1; ++j) {
     const double* lk = ws_link(d.ws, n, J, j);
     if (j + 1 < J - 1 && row) {
-      const double* F = ws_link(d.ws, n, J, j + 1) + lane * n;
+      const double* F = ws_link(d.ws, n, J, j + 1) + lane;
 #pragma unroll
-      for (int k = 0; k < MN; ++k) nxt[k] = k < n ? F[k] : 0.0;
+      for (int k = 0; k < MN; ++k) nxt[k] = k < n ? F[k * n] : 0.0;
     }
-    double acc = row ? lk[n * n + lane] : 0.0;
+    // four accumulation chains
+    double acc[4] = {row ? lk[n * n + lane] : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < MN; ++k) acc = fma(cur[k], sx[k < n ? k : 0], acc);
+    for (int k = 0; k < MN; ++k) acc[k & 3] = fma(cur[k], sx[k < n ? k : 0], acc[k & 3]);
+    const double xn = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (row) {
-      sx[lane] = acc;
-      ws_bnd(d.ws, n, J, j + 1)[n * n + n + lane] = acc;
+      sx[lane] = xn;
+      ws_bnd(d.ws, n, J, j + 1)[n * n + n + lane] = xn;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();

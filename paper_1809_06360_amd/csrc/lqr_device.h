@@ -641,7 +641,7 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
 }
 
 // Linking solve. With (Pn, pn) the exact value at t_{j+1} and N = I + Psi_j Pn:
-//   [F | f] = N^{-1} [Gam_j' | psi_j - Psi_j pn]   (explicit inverse, one wave)
+//   [F | f] = N^{-1} [Gam_j' | psi_j - Psi_j pn]   (explicit inverse, wg_invert)
 //   P_{t_j} = P0_j + Gam_j Pn F,   p_{t_j} = pbar_j + Gam_j (pn + Pn f)
 // which is the elimination of x_{t_{j+1}} and the link multiplier
 // mu_j = (I + Pn Psi_j)^{-1}(Pn (Gam_j' x + psi_j) + pn) from the segment's
@@ -654,14 +654,14 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   double* sPn = smem;        // exact value at t_{j+1}
   double* sA1 = sPn + blk;   // Psi, then Gam
   double* sN = sA1 + blk;    // N, column-major -> its inverse in place -> T1 = Pn F
-  double* sF = sN + blk;     // F
+  double* sF = sN + blk;     // F' (row c holds column c of F)
   double* spn = sF + blk;
   double* sv = spn + n;      // w = psi - Psi pn, then pn + Pn f
   double* sf = sv + n;
   double* sx = sf + n;
   double* sxn = sx + n;
-  double* rowbuf = sxn + n;
-  int* flag = reinterpret_cast<int*>(rowbuf + MN);
+  const InvExchange ix = carve_inv_exchange(sxn + n);
+  int* flag = reinterpret_cast<int*>(sxn + n + kInvExchangeDoubles);
 
   if (threadIdx.x == 0) {
     int f = 0;
@@ -687,31 +687,28 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
                                           [=](int i, int jj, double v) {
                                             sN[jj * L + i] = v + (i == jj ? 1.0 : 0.0);
                                           });
-    gemv2(n, n, sA1, L, spn, 0, spn, 0, spn, [=](int i, double v) { sv[i] = psi[i] - v; });
+    gemv_wave(1, n, n, sA1, L, spn, [=](int i, double v) { sv[i] = psi[i] - v; });
     __syncthreads();
     load_block(sA1, L, Gam, n, n, n);  // Psi no longer needed
-    if (threadIdx.x < 64) {
-      const int bad = wave_invert<MN>(sN, L, n, sN, L, rowbuf);
-      if (threadIdx.x == 0 && bad && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
-    }
-    __syncthreads();
+    const int bad = wg_invert<MN>(sN, L, n, sN, L, ix);
+    if (threadIdx.x == 0 && bad && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
     // [F | f] = N^{-1} [Gam' | w], kept in LDS and written to the workspace
-    // for the forward pass
+    // (F column-major) for the forward pass: F' = Gam N^{-T}
     double* lk = ws_link(d.ws, n, J, j);
-    pgemm_sub<fp64_engine(E), true, true, false, false>(n, n, n, sN, L, sA1, L, 0, sN, L, sA1, L,
-        [=](int i, int jj, double v) {
-          sF[i * L + jj] = v;
-          lk[i * n + jj] = v;
+    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sN, L, 0, sA1, L, sN, L,
+        [=](int c, int i, double v) {
+          sF[c * L + i] = v;
+          lk[c * n + i] = v;
         });
-    gemv_cm(n, n, sN, L, sv, [=](int i, double v) {
+    gemv_cm_wave(1, n, n, sN, L, sv, [=](int i, double v) {
       sf[i] = v;
       lk[n * n + i] = v;
     });
     __syncthreads();
     // T1 = Pn F -> sN ;  v = pn + Pn f
-    pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sPn, L, sF, L, 0, sPn, L, sF, L,
+    pgemm_sub<fp64_engine(E), false, true, false, false>(n, n, n, sPn, L, sF, L, 0, sPn, L, sF, L,
                                          [=](int i, int jj, double v) { sN[i * L + jj] = v; });
-    gemv2(n, n, sPn, L, sf, 0, spn, 0, spn, [=](int i, double v) { sv[i] = spn[i] + v; });
+    gemv_wave(1, n, n, sPn, L, sf, [=](int i, double v) { sv[i] = spn[i] + v; });
     __syncthreads();
     pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sN, L, 0, sA1, L, sN, L,
         [=](int i, int jj, double v) {
@@ -722,7 +719,7 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
           }
         },
         SkipUpper{n});
-    gemv2(n, n, sA1, L, sv, 0, sv, 0, sv, [=](int i, double v) { spn[i] = pbar[i] + v; });
+    gemv_wave(1, n, n, sA1, L, sv, [=](int i, double v) { spn[i] = pbar[i] + v; });
     __syncthreads();
     double* b = ws_bnd(d.ws, n, J, j);
     store_block(b, n, sPn, L, n, n);
@@ -736,7 +733,7 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   __syncthreads();
   for (int j = 0; j < J - 1; ++j) {
     const double* lk = ws_link(d.ws, n, J, j);
-    gemv2(n, n, lk, n, sx, 0, sx, 0, sx, [=](int i, double v) { sxn[i] = lk[n * n + i] + v; });
+    gemv_cm_wave(0, n, n, lk, n, sx, [=](int i, double v) { sxn[i] = lk[n * n + i] + v; });
     __syncthreads();
     double* xb = ws_bnd(d.ws, n, J, j + 1) + n * n + n;
     for (int i = threadIdx.x; i < n; i += kThreads) {

@@ -107,7 +107,9 @@ LQR_HD int seg_begin(int T, int J, int j) {
 // Workspace strides, in doubles.
 //  seg[j], j < J-1 : P0 (n*n) | Gamma (n*n) | Psi (n*n) | pbar (n) | psi (n)
 //  bnd[j], j < J   : P (n*n) | p (n) | x (n)           value and state at seg_begin(j)
-//  link[j], j < J-1: F (n*n) | f (n)                   x_{t_{j+1}} = F x_{t_j} + f
+//  link[j], j < J-1: F (n*n, column-major) | f (n)     x_{t_{j+1}} = F x_{t_j} + f
+//                    (column-major so that the serial forward chain, lane i
+//                    taking row i, reads each column with one coalesced load)
 LQR_HD size_t seg_stride(int n) { return 3 * (size_t)n * n + 2 * (size_t)n; }
 LQR_HD size_t bnd_stride(int n) { return (size_t)n * n + 2 * (size_t)n; }
 LQR_HD size_t link_stride(int n) { return (size_t)n * n + (size_t)n; }
@@ -210,6 +212,10 @@ LQR_HD size_t couple_lds(int n, int nw);
 // width per product engine (MFMA variants serve n <= 64, VALU ones n < 32).
 LQR_HD constexpr int persist_nw(bool mf) { return mf ? 64 : 32; }
 
+// Doubles of LDS for the workgroup inversion's exchange (wg_invert): two
+// slots of 64 multipliers, two reciprocal pivots, two pivot rows and a flag.
+constexpr int kInvExchangeDoubles = 132;
+
 // Leading dimension of an n x n block in LDS: odd, so that the 16 lanes of a
 // matrix-core operand fragment that walk a strided row or column of the block
 // hit distinct LDS banks.
@@ -218,12 +224,12 @@ LQR_HD constexpr int ld_odd(int n) { return n | 1; }
 // Join of two summaries: the four n x n operands staged in LDS (register
 // widths up to 48; wider joins read them from global memory), four n x n
 // work blocks (M and its inverse, the right-hand side, and two products of
-// the inverse), four vectors, the inversion's row buffer and a flag word.
+// the inverse), four vectors and the inversion's exchange.
 LQR_HD constexpr bool link_tree_staged(int nw) { return nw <= 48; }
 
 LQR_HD size_t link_tree_lds(int n, int nw) {
   const size_t blk = (size_t)n * ld_odd(n);
-  const size_t dbl = (link_tree_staged(nw) ? 8 : 4) * blk + 4 * (size_t)n + (size_t)nw + 2;
+  const size_t dbl = (link_tree_staged(nw) ? 8 : 4) * blk + 4 * (size_t)n + kInvExchangeDoubles;
   return dbl * 8 + 64;
 }
 
@@ -273,9 +279,9 @@ LQR_HD size_t rollout_lds(int /*n*/, int /*m*/) { return (4 * 128 + 4 * 64) * 8 
 
 // `nw` is the register width of the kernel variant (pad_rows of the largest n).
 // Four n x n blocks (exact value, Psi then Gam, N then its inverse, F), five
-// vectors, the inversion's row buffer and three flag words.
-LQR_HD size_t couple_lds(int n, int nw) {
-  const size_t dbl = 4 * (size_t)n * ld_odd(n) + 5 * (size_t)n + (size_t)nw;
+// vectors, the inversion's exchange and two flag words.
+LQR_HD size_t couple_lds(int n, int /*nw*/) {
+  const size_t dbl = 4 * (size_t)n * ld_odd(n) + 5 * (size_t)n + kInvExchangeDoubles;
   return dbl * 8 + 4 * 4 + 64;
 }
 

@@ -192,12 +192,42 @@ LQR_DEV T wave_sum(T v) {
 
 // ---------------------------------------------------------------------------
 // y(i) = epi(i, sum_l M1[i][l] v1[l] + sum_l M2[i][l] v2[l]) for i < rows.
-// M1, M2 may live in global memory or LDS; v1, v2 in LDS. One wave per row,
-// lanes stride the columns (coalesced row reads), wave-reduced.
+// M1, M2 may live in global memory or LDS; v1, v2 in LDS. Up to 64 rows, four
+// lanes share a row (consecutive columns, so a load instruction covers 16 rows
+// x 32 bytes) and their partial sums meet by two quad permutations; longer
+// matrices take one wave per row with a wave reduction.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+LQR_DEV double quad_xor(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename T, typename Epi>
 LQR_DEV void gemv2(int rows, int c1, const T* M1, int ld1, const T* v1,
                    int c2, const T* M2, int ld2, const T* v2, Epi epi) {
+  static_assert(kThreads == 256, "four lanes per row for 64 rows");
+  if (rows <= 64) {
+    const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int r = i < rows ? i : 0;
+    T s0 = T(0), s1 = T(0);
+    const T* a1 = M1 + (size_t)r * ld1;
+    const T* a2 = M2 + (size_t)r * ld2;
+    int l = q;
+    for (; l + 4 < c1; l += 8) {
+      s0 = fma(a1[l], v1[l], s0);
+      s1 = fma(a1[l + 4], v1[l + 4], s1);
+    }
+    if (l < c1) s0 = fma(a1[l], v1[l], s0);
+    for (l = q; l < c2; l += 4) s1 = fma(a2[l], v2[l], s1);
+    T s = s0 + s1;
+    s += quad_xor<0xB1>(s);  // quad_perm 1,0,3,2
+    s += quad_xor<0x4E>(s);  // quad_perm 2,3,0,1
+    if (q == 0 && i < rows) epi(i, s);
+    return;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = wave; i < rows; i += kWaves) {
     T s = T(0);
@@ -208,22 +238,41 @@ LQR_DEV void gemv2(int rows, int c1, const T* M1, int ld1, const T* v1,
   }
 }
 
-// y(i) = epi(i, sum_l A[l * lda + i] v[l]) for i < rows <= kThreads: a
-// column-major A (or the transpose of a row-major block); thread i walks row i
-// with two accumulation chains.
-template <typename T, typename Epi>
-LQR_DEV void gemv_cm(int rows, int cols, const T* A, int lda, const T* v, Epi epi) {
-  const int i = threadIdx.x;
-  if (i < rows) {
-    T s0 = T(0), s1 = T(0);
-    int l = 0;
-    for (; l + 1 < cols; l += 2) {
-      s0 = fma(A[l * lda + i], v[l], s0);
-      s1 = fma(A[(l + 1) * lda + i], v[l + 1], s1);
-    }
-    if (l < cols) s0 = fma(A[l * lda + i], v[l], s0);
-    epi(i, s0 + s1);
+// Matrix-vector products of at most 64 rows by the 64 lanes of ONE wave
+// (`w`; lane i takes row i, four accumulation chains), for blocks in LDS or
+// walked along coalesced columns: no cross-lane reduction, so a product costs
+// about `cols` dependent loads and multiply-adds, and products handed to
+// different waves run side by side.
+//   gemv_wave:    y(i) = epi(i, sum_l M[i * ld + l] v[l])   (row-major M)
+//   gemv_cm_wave: y(i) = epi(i, sum_l A[l * lda + i] v[l])  (column-major A,
+//                 or the transpose of a row-major block)
+template <bool ColMajor, typename T, typename Epi>
+LQR_DEV void gemv_lanes(int w, int rows, int cols, const T* A, int ld, const T* v, Epi epi) {
+  if ((int)(threadIdx.x >> 6) != w) return;
+  const int i = threadIdx.x & 63;
+  const int r = i < rows ? i : 0;
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+  const T* a = ColMajor ? A + r : A + (size_t)r * ld;
+  const int st = ColMajor ? ld : 1;
+  int l = 0;
+  for (; l + 3 < cols; l += 4) {
+    s0 = fma(a[l * st], v[l], s0);
+    s1 = fma(a[(l + 1) * st], v[l + 1], s1);
+    s2 = fma(a[(l + 2) * st], v[l + 2], s2);
+    s3 = fma(a[(l + 3) * st], v[l + 3], s3);
   }
+  for (; l < cols; ++l) s0 = fma(a[l * st], v[l], s0);
+  if (i < rows) epi(i, (s0 + s1) + (s2 + s3));
+}
+
+template <typename T, typename Epi>
+LQR_DEV void gemv_wave(int w, int rows, int cols, const T* M, int ld, const T* v, Epi epi) {
+  gemv_lanes<false>(w, rows, cols, M, ld, v, epi);
+}
+
+template <typename T, typename Epi>
+LQR_DEV void gemv_cm_wave(int w, int rows, int cols, const T* A, int lda, const T* v, Epi epi) {
+  gemv_lanes<true>(w, rows, cols, A, lda, v, epi);
 }
 
 // ---------------------------------------------------------------------------
@@ -417,25 +466,29 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
 }
 
 // ---------------------------------------------------------------------------
-// Inverse of an n x n matrix (n <= MAXN <= 64) by ONE wave, with no workgroup
-// barrier: Gauss-Jordan exchange steps with row pivoting. Lane i keeps row i
-// of the working table in registers; step k pivots column k on the unused row
-// p of largest magnitude (a max-reduction over lanes), lane p hands its row to
-// the wave through `rowbuf` (LDS, ordered by the wave's own in-order LDS
-// queue) and every other row i takes
+// Inverse of an n x n matrix (n <= 64) by Gauss-Jordan exchange steps with
+// row pivoting (wg_invert below). Lane i of every wave holds row i of the
+// working table; step k pivots column k on the unused row p of largest
+// magnitude and every other row i takes
 //   a(i, j) -= a(i, k)/a(p, k) * a(p, j)  (j != k),   a(i, k) /= a(p, k).
-// The exchange would also scale the pivot row by -1/a(p, k); that scale is
-// kept aside per lane (sigma) and applied once at the end, so a step costs
-// one fused multiply-add per element on every lane alike (later steps treat
-// the stored row exactly, since the scale cancels from their updates). After
-// n steps lane i holds row step(i) of the inverse with its columns in pivot
-// order: inverse(step(i), p_k) = sigma_i * a(i, k).
-// Input element (i, j) at A[j * lda + i]; the inverse goes to Ainv with the
-// same column-major convention (Ainv may be A: all of A is read before any
-// write). A zero or non-finite pivot yields NaN results and returns 1.
-// Called by the 64 lanes of one wave together; the caller orders the producer
-// of A and the consumers of Ainv with workgroup barriers.
+// The exchange would also scale the pivot row by -1/a(p, k) (and set its
+// pivot entry to 1/a(p, k)); that scale is kept aside per row (sigma, with
+// the stored pivot entry -1) and applied once at the end, so a step costs one
+// fused multiply-add per element on every lane alike: later steps treat the
+// stored row exactly, since the scale cancels from their updates. After n
+// steps row i of the table holds row step(i) of the inverse with its columns
+// in pivot order: inverse(step(i), p_k) = sigma_i * a(i, k).
 // ---------------------------------------------------------------------------
+// 1/d by the hardware reciprocal estimate and two Newton steps (quadratic
+// convergence from its ~2^-23 relative error: well below 1 ulp of FP64 after
+// the second step; exact reciprocals of powers of two). Used where the
+// reciprocal is on a serial chain; d is finite and nonzero or NaN.
+LQR_DEV double recip(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(x, fma(-d, x, 1.0), x);
+  return fma(x, fma(-d, x, 1.0), x);
+}
+
 // Largest unsigned value over the wave (all 64 lanes active).
 LQR_DEV unsigned wave_max_u32(unsigned v) {
   unsigned o;
@@ -469,75 +522,133 @@ LQR_DEV void static_for(F&& f) {
   }
 }
 
-template <int MAXN>
-LQR_DEV int wave_invert(const double* A, int lda, int n, double* Ainv, int ldi, double* rowbuf) {
-  static_assert(MAXN <= 64, "one row per lane");
+// ---------------------------------------------------------------------------
+// The inverse by the four waves of the workgroup: wave w keeps the
+// columns j = w, w + 4, ... of the working table (lane i = row i, as above),
+// so each step's updates are spread over the four SIMDs; one workgroup
+// barrier per step. In step k the wave owning column k + 1 (already updated
+// by the steps before k) applies step k to that column first, searches the
+// next pivot and publishes its row and the multipliers -a(i, k+1)/a(p, k+1)
+// of every row to the double-buffered exchange `xb` (2 * 64 doubles, 2
+// doubles and 2 ints of LDS) before updating its other columns, so the
+// search overlaps the other waves' updates. Every wave tracks the per-row
+// scale, pivot step and pivot rows from what is published. Input element
+// (i, j) at A[j * lda + i]; the inverse goes to Ainv with the same
+// column-major convention (Ainv may be A: all of A is read before any write).
+// A zero or non-finite pivot yields NaN results and returns 1. Called by all
+// kThreads threads together; starts and ends with a workgroup barrier.
+// ---------------------------------------------------------------------------
+struct InvExchange {
+  double* c;   // 2 x 64 multipliers
+  double* iv;  // 2 reciprocal pivots
+  int* p;      // 2 pivot rows
+  int* bad;
+};
+
+LQR_DEV InvExchange carve_inv_exchange(double* base) {
+  InvExchange x;
+  x.c = base;
+  x.iv = base + 128;
+  x.p = reinterpret_cast<int*>(base + 130);
+  x.bad = x.p + 2;
+  return x;
+}
+static_assert(kInvExchangeDoubles == 132, "exchange layout");
+
+// Body of wave W (compile-time, so that every column index is a constant).
+template <int MAXN, int W>
+LQR_DEV int wg_invert_wave(const double* A, int lda, int n, double* Ainv, int ldi, InvExchange x) {
+  constexpr int NC = (MAXN + 3) / 4;  // columns per wave
   const int lane = threadIdx.x & 63;
   const bool live = lane < n;
-  // Rows past n (lanes that never pivot) and columns past n are padding: they
-  // load clamped copies and are never read back into the first n columns.
   const int row = live ? lane : 0;
-  double a[MAXN];
+  __syncthreads();  // A is complete
+  double a[NC];
 #pragma unroll
-  for (int j = 0; j < MAXN; ++j) a[j] = A[(j < n ? j : n - 1) * lda + row];
+  for (int q = 0; q < NC; ++q) {
+    const int j = 4 * q + W;
+    a[q] = A[(j < n ? j : n - 1) * lda + row];
+  }
   bool used = !live;
-  int step = 0, prow = 0, bad = 0;
+  int step = 0, prow = 0;
   double sigma = 1.0;
+  // pivot search on a column held by this wave; publishes the pivot row, its
+  // reciprocal and the multipliers of every row into slot s
+  auto search = [&](double v, int s) {
+    const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, v) >> 32) & 0x7fffffffu;
+    const unsigned key = wave_max_u32(used ? 0u : ((hi & ~63u) | (unsigned)(63 - lane)) + 64u);
+    const int p = 63 - (int)(key & 63u);
+    double piv = readlane(v, p);
+    const bool ok = (piv != 0.0) && isfinite(piv);
+    piv = ok ? piv : qnan<double>();
+    const double inv = recip(piv);
+    x.c[s * 64 + lane] = row == p ? 0.0 : -v * inv;
+    if (lane == 0) {
+      x.iv[s] = inv;
+      x.p[s] = p;
+      if (!ok) *x.bad = 1;
+    }
+  };
+  if constexpr (W == 0) {
+    if (lane == 0) *x.bad = 0;
+    search(a[0], 0);
+  }
+  __syncthreads();
   static_for<0, MAXN>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if (k < n) {
-      // pivot: largest |a(i, k)| over unused rows. Key = high word of |a|
-      // (exponent and leading mantissa bits) with its low 6 bits replaced by
-      // 63 - lane (ties go to the lowest row), offset so that any unused row
-      // outranks the used ones; NaN and infinity rank first.
-      const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, a[k]) >> 32) & 0x7fffffffu;
-      const unsigned key = wave_max_u32(used ? 0u : ((hi & ~63u) | (unsigned)(63 - lane)) + 64u);
-      const int p = 63 - (int)(key & 63u);
-      double piv = readlane(a[k], p);
-      if (!(piv != 0.0) || !isfinite(piv)) {
-        bad = 1;
-        piv = qnan<double>();
-      }
-      const double inv = 1.0 / piv;
-      const bool isp = lane == p;
-      // the previous step's reads of rowbuf precede this store, and the store
-      // precedes this step's reads (LDS is in order within a wave; the fences
-      // keep the compiler from moving the accesses across lanes' boundaries)
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (isp) {
-#pragma unroll
-        for (int j = 0; j < MAXN; ++j) rowbuf[j] = a[j];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      // the whole pivot row is requested before the first use
-      double r[MAXN];
-#pragma unroll
-      for (int j = 0; j < MAXN; ++j) r[j] = rowbuf[j];
-      __builtin_amdgcn_sched_barrier(0);
-      const double g = a[k] * inv;
-      const double c = isp ? 0.0 : -g;
-#pragma unroll
-      for (int j = 0; j < MAXN; ++j)
-        if (j != k) a[j] = fma(c, r[j], a[j]);
-      a[k] = isp ? -1.0 : g;
+      constexpr int s = k & 1;
+      // the owner of column k + 1 applies step k to it first and publishes
+      // the next pivot before its other columns
+      constexpr int qn = (k + 1) / 4;
+      constexpr bool owner = ((k + 1) & 3) == W && qn < NC;
+      const double c = x.c[s * 64 + lane];
+      const double inv = x.iv[s];
+      const int p = __builtin_amdgcn_readfirstlane(x.p[s]);
+      const bool isp = row == p;
       if (isp) {
         sigma = -inv;
         used = true;
         step = k;
       }
       if (lane == k) prow = p;
+      if constexpr (owner) {
+        a[qn] = fma(c, readlane(a[qn], p), a[qn]);
+        if (k + 1 < n) search(a[qn], s ^ 1);
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (4 * q + W == k)
+          a[q] = isp ? -1.0 : -c;
+        else if (!(owner && q == qn))
+          a[q] = fma(c, readlane(a[q], p), a[q]);
+      }
+      __syncthreads();
     }
   });
+  // column j = 4q + W of the table is column p_j of the inverse
 #pragma unroll
-  for (int k = 0; k < MAXN; ++k) {
-    if (k < n) {
-      const int col = __builtin_amdgcn_readlane(prow, k);
-      if (live) Ainv[col * ldi + step] = sigma * a[k];
+  for (int q = 0; q < NC; ++q) {
+    const int j = 4 * q + W;
+    if (j < n) {
+      const int col = __builtin_amdgcn_readlane(prow, j);
+      if (live) Ainv[col * ldi + step] = sigma * a[q];
     }
   }
+  const int bad = *x.bad;
+  __syncthreads();
   return bad;
+}
+
+template <int MAXN>
+LQR_DEV int wg_invert(const double* A, int lda, int n, double* Ainv, int ldi, InvExchange x) {
+  static_assert(MAXN <= 64 && kWaves == 4, "one row per lane, four waves");
+  switch (threadIdx.x >> 6) {
+    case 0: return wg_invert_wave<MAXN, 0>(A, lda, n, Ainv, ldi, x);
+    case 1: return wg_invert_wave<MAXN, 1>(A, lda, n, Ainv, ldi, x);
+    case 2: return wg_invert_wave<MAXN, 2>(A, lda, n, Ainv, ldi, x);
+    default: return wg_invert_wave<MAXN, 3>(A, lda, n, Ainv, ldi, x);
+  }
 }
 
 // ---------------------------------------------------------------------------

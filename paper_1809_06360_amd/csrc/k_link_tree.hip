@@ -31,10 +31,24 @@ namespace {
 
 LQR_DEV double* scan_elem(double* buf, int n, int j) { return buf + (size_t)j * seg_stride(n); }
 
+// Element e of a round's input: the first round (dist == 1) reads the phase-1
+// summaries in place (segments j < J-1, and the last segment's exact value
+// from its boundary slot, whose linear term sits right after P); later rounds
+// read the scan buffer. `poff` returns the offset of the element's pbar.
+LQR_DEV const double* round_elem(const InstDesc& d, const double* in, int dist, int e, int& poff) {
+  const int n = d.n, J = d.J, nn = n * n;
+  poff = 3 * nn;
+  if (dist > 1) return scan_elem(const_cast<double*>(in), n, e);
+  if (e < J - 1) return ws_seg(d.ws, n, e);
+  poff = nn;
+  return ws_bnd(d.ws, n, J, J - 1);
+}
+
 }  // namespace
 
 // Scan buffer 0: elements j < J-1 are the phase-1 summaries, element J-1 the
-// last segment's exact value; the instance's linking flag is cleared.
+// last segment's exact value; the instance's linking flag is cleared (used by
+// the large-state linking solve; the scan below reads the summaries in place).
 __global__ __launch_bounds__(kThreads) void k_link_init(InstDesc d) {
   const int n = d.n, J = d.J, j = blockIdx.x;
   double* dst = scan_elem(ws_scan(d.ws, n, J, 0), n, j);
@@ -65,17 +79,18 @@ __global__ __launch_bounds__(kThreads) void k_link_combine(InstDesc d, int dist,
   extern __shared__ double smem[];
   const int n = d.n, J = d.J, j = blockIdx.x;
   const int nn = n * n, L = ld_odd(n), blk = n * L;
-  const double* a = scan_elem(const_cast<double*>(in), n, j);
+  int apo, bpo;
+  const double* a = round_elem(d, in, dist, j, apo);
   double* o = scan_elem(out, n, j);
   if (j + dist >= J) {
     for (int e = threadIdx.x; e < nn; e += kThreads) o[e] = a[e];
-    for (int i = threadIdx.x; i < n; i += kThreads) o[3 * nn + i] = a[3 * nn + i];
+    for (int i = threadIdx.x; i < n; i += kThreads) o[3 * nn + i] = a[apo + i];
     return;
   }
-  const double* b = scan_elem(const_cast<double*>(in), n, j + dist);
+  const double* b = round_elem(d, in, dist, j + dist, bpo);
   const bool exact_b = j + 2 * dist - 1 >= J - 1;
-  const double *P0a = a, *pa = a + 3 * nn, *psa = pa + n;
-  const double *Psb = b + 2 * nn, *pb = b + 3 * nn, *psb = pb + n;
+  const double *P0a = a, *pa = a + apo, *psa = pa + n;
+  const double *Psb = b + 2 * nn, *pb = b + bpo, *psb = pb + n;
   const double *Ga = a + nn, *Psa = a + 2 * nn, *P0b = b, *Gb = b + nn;
   int lg = n;  // leading dimension of the four operands
   double* sM = smem;       // M, column-major -> Mi in place -> U = V Gam_b
@@ -204,57 +219,99 @@ __global__ __launch_bounds__(kThreads) void k_link_maps(InstDesc d, const double
 
 // Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, and the
 // instance's info word (a stage failure of phase 1 takes precedence). The
-// chain is serial and latency-bound, so it runs in one wave: lane i keeps row
-// i of F_j in registers (row i of F_{j+1} is loaded while step j computes;
-// with F column-major each of those loads is one coalesced column) and the
-// state vector is exchanged through LDS with wave-level ordering.
+// chain is serial and latency-bound: wave 0 runs it from LDS (lane i takes
+// row i of F_j, F column-major so the lanes read consecutive words; the state
+// vector is exchanged through LDS with wave-level ordering and the new states
+// are kept in LDS), while waves 1..3 write the previous chunk's states out and
+// copy the next chunk of S link maps from global memory into the other half of
+// a double buffer with coalesced loads; one workgroup barrier per chunk, so a
+// global round trip is paid once per S steps instead of once per step.
 template <int MN>
-__global__ __launch_bounds__(64) void k_link_forward(InstDesc d) {
+__global__ __launch_bounds__(kThreads) void k_link_forward(InstDesc d) {
   extern __shared__ double smem[];
-  const int n = d.n, J = d.J, lane = threadIdx.x;
-  double* sx = smem;
+  const int n = d.n, J = d.J, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int S = link_forward_slots(n);
+  const size_t ls = link_stride(n);
+  const int steps = J - 1;
+  double* sx = smem;                           // 64
+  double* sst = smem + 64;                     // 2 x S boundary states (64 each)
+  double* buf = sst + 2 * (size_t)S * 64;      // 2 x S link maps
+  // boundary states of chunk c, written to the workspace by threads t0..
+  auto flush_states = [&](int c, int t0, int nt) {
+    if (c < 0) return;
+    const int cnt = min(S, steps - c * S);
+    const double* st = sst + (size_t)(c & 1) * S * 64;
+    for (int e = threadIdx.x - t0; e < cnt * n; e += nt) {
+      const int u = e / n, i = e - u * n;
+      ws_bnd(d.ws, n, J, c * S + u + 1)[n * n + n + i] = st[u * 64 + i];
+    }
+  };
+  auto copy_chunk = [&](int c, int t0, int nt) {  // chunk c by threads t0.. (nt of them)
+    const int j0 = c * S, cnt = min(S, steps - j0);
+    if (cnt <= 0) return;
+    const double* src = ws_link(d.ws, n, J, j0);  // link maps are contiguous
+    double* dst = buf + (size_t)(c & 1) * S * ls;
+    const size_t total = (size_t)cnt * ls;
+    // up to 64 loads in flight per thread, which covers a whole chunk for
+    // every n (clamped indices: no branch per load)
+    constexpr int U = 64;
+    for (size_t e0 = threadIdx.x - t0; e0 < total; e0 += (size_t)U * nt) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t e = e0 + (size_t)u * nt;
+        v[u] = src[e < total ? e : total - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t e = e0 + (size_t)u * nt;
+        if (e < total) dst[e] = v[u];
+      }
+    }
+  };
   const bool row = lane < n;
-  const double xi0 = row ? d.x0[lane] : 0.0;
-  if (row) {
+  const int r = row ? lane : 0;
+  if (wave == 0) {  // entries past n stay zero: padding columns contribute nothing
+    const double xi0 = row ? d.x0[lane] : 0.0;
     sx[lane] = xi0;
-    ws_bnd(d.ws, n, J, 0)[n * n + n + lane] = xi0;
+    if (row) ws_bnd(d.ws, n, J, 0)[n * n + n + lane] = xi0;
   }
-  double cur[MN], nxt[MN];
+  copy_chunk(0, 0, kThreads);
+  __syncthreads();
+  const int chunks = (steps + S - 1) / S;
+  for (int c = 0; c < chunks; ++c) {
+    if (wave > 0) {
+      flush_states(c - 1, 64, kThreads - 64);
+      copy_chunk(c + 1, 64, kThreads - 64);
+    } else {
+      double* st = sst + (size_t)(c & 1) * S * 64;
+      const double* slots = buf + (size_t)(c & 1) * S * ls;
+      const int cnt = min(S, steps - c * S);
+      for (int u = 0; u < cnt; ++u) {
+        const double* F = slots + (size_t)u * ls;
+        double f[MN];
 #pragma unroll
-  for (int k = 0; k < MN; ++k) nxt[k] = 0.0;
+        for (int k = 0; k < MN; ++k) f[k] = F[(k < n ? k : 0) * n + r];
+        __builtin_amdgcn_sched_barrier(0);
+        // four accumulation chains
+        double acc[4] = {F[(size_t)n * n + r], 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < MN; ++k) cur[k] = 0.0;
-  if (J > 1 && row) {
-    const double* F = ws_link(d.ws, n, J, 0) + lane;
-#pragma unroll
-    for (int k = 0; k < MN; ++k) cur[k] = k < n ? F[k * n] : 0.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int j = 0; j < J - 1; ++j) {
-    const double* lk = ws_link(d.ws, n, J, j);
-    if (j + 1 < J - 1 && row) {
-      const double* F = ws_link(d.ws, n, J, j + 1) + lane;
-#pragma unroll
-      for (int k = 0; k < MN; ++k) nxt[k] = k < n ? F[k * n] : 0.0;
+        for (int k = 0; k < MN; ++k) acc[k & 3] = fma(f[k], sx[k], acc[k & 3]);
+        const double xn = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (row) {
+          sx[lane] = xn;
+          st[u * 64 + lane] = xn;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
     }
-    // four accumulation chains
-    double acc[4] = {row ? lk[n * n + lane] : 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < MN; ++k) acc[k & 3] = fma(cur[k], sx[k < n ? k : 0], acc[k & 3]);
-    const double xn = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (row) {
-      sx[lane] = xn;
-      ws_bnd(d.ws, n, J, j + 1)[n * n + n + lane] = xn;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < MN; ++k) cur[k] = nxt[k];
+    __syncthreads();
   }
-  if (lane == 0) {
+  flush_states(chunks - 1, 0, kThreads);
+  if (threadIdx.x == 0) {
     int f = 0;
     for (int j = 0; j < J; ++j) f = combine_info(f, d.fail[j]);
     *d.info = f ? f : d.fail[J];
@@ -282,9 +339,7 @@ hipError_t launch_link_init(const InstDesc& d, hipStream_t stream) {
 
 hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
   const int J = d.J, n = d.n;
-  hipLaunchKernelGGL(k_link_init, dim3(J), dim3(kThreads), 0, stream, d);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   int src = 0;
   for (int dist = 1; dist < J; dist *= 2) {
     const double* in = ws_scan(d.ws, n, J, src);
@@ -307,7 +362,10 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream) {
   });
   if (e != hipSuccess) return e;
   return with_link_variant<k_link_forward_ref>(n, [&](auto k) -> hipError_t {
-    hipLaunchKernelGGL(k, dim3(1), dim3(64), 64 * sizeof(double), stream, d);
+    const size_t lds = link_forward_lds(n);
+    hipError_t e2 = ensure_dynamic_lds((const void*)k, lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(k, dim3(1), dim3(kThreads), lds, stream, d);
     return hipGetLastError();
   });
 }

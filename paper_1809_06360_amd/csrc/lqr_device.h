@@ -637,7 +637,10 @@ LQR_DEV void phase1_item(const InstDesc& d, int seg, double* smem) {
     store_block(b, n, s.P, s.ldp, n, n);
     for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = s.p[i];
   }
-  if (threadIdx.x == 0) d.fail[seg] = fail;
+  if (threadIdx.x == 0) {
+    d.fail[seg] = fail;
+    if (seg == 0) d.fail[J] = 0;  // the linking-failure word, raised by phase 2
+  }
 }
 
 // Linking solve. With (Pn, pn) the exact value at t_{j+1} and N = I + Psi_j Pn:

@@ -233,6 +233,18 @@ LQR_HD size_t link_tree_lds(int n, int nw) {
   return dbl * 8 + 64;
 }
 
+// Forward chain over the boundaries: double-buffered chunks of S link maps
+// (link_stride(n) doubles each) and of their S boundary states (64 doubles
+// each), within about 150 KiB, and the state vector.
+LQR_HD int link_forward_slots(int n) {
+  const size_t per = (size_t)n * n + n + 64;
+  const size_t s = (150u * 1024u / 8u - 64u) / (2 * per);
+  return s < 1 ? 1 : (s > 16 ? 16 : (int)s);
+}
+LQR_HD size_t link_forward_lds(int n) {
+  return (64 + 2 * (size_t)link_forward_slots(n) * ((size_t)n * n + n + 64)) * 8;
+}
+
 // ---------------------------------------------------------------------------
 // Large-state path (65..128 states, up to 64 inputs; 256-thread sweep and
 // 512-thread linking workgroups).

@@ -268,6 +268,24 @@ lqr_status_t lqr_workspace_layout(const lqr_problem_t *probs, int32_t batch,
  * on one stream is enough. */
 lqr_status_t lqr_solve_noalloc(const lqr_problem_t *prob, const lqr_options_t *opts, void *stream);
 
+/* Link multipliers of a solved instance (Sec. II-A: the multiplier of each
+ * segment's end-point constraint x_{t_{j+1}} = x_term, matched across the link
+ * equation; Sec. II-B, eq. mu): mu_j = P_{t_{j+1}} x_{t_{j+1}} + p_{t_{j+1}},
+ * j = 0..J-2, the value gradient at the link point t_{j+1} = (j+1) floor(T/J)
+ * + min(j+1, T mod J) (the segment split lqr_solve uses). In the paper's sign
+ * convention the segment's dynamics multipliers are the negated costates, and
+ * mu_j is the costate at the link point itself. prob: HOST descriptor whose
+ * outputs P, p and x hold a finished solve of this instance, read on the
+ * device (P, p and x must not be NULL); segments: the J of that solve (the
+ * descriptor's, or lqr_plan_segments' choice when it was 0), 1 <= J <= T; mu:
+ * DEVICE [J-1][n] output in the outputs' precision (FP32 with
+ * LQR_PREC_FP32, else FP64); nothing is written for J = 1. One workgroup per
+ * link point, stream-ordered after the solve on `stream`. Returns
+ * LQR_ERR_INVALID_ARG for NULL pointers, J outside 1..T or n above 128,
+ * LQR_ERR_HIP if the launch fails. */
+lqr_status_t lqr_link_multipliers(const lqr_problem_t *prob, const lqr_options_t *opts,
+                                  int32_t segments, void *mu, void *stream);
+
 /* Static description of a status code. */
 const char *lqr_status_string(lqr_status_t status);
 

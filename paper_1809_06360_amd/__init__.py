@@ -56,7 +56,7 @@ class LqrGrad(ctypes.Structure):
 
 EXPORTS = ("lqr_workspace_size", "lqr_workspace_layout", "lqr_plan_segments", "lqr_solve",
            "lqr_solve_noalloc", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward",
-           "lqr_status_string")
+           "lqr_link_multipliers", "lqr_status_string")
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _lib = None
@@ -90,6 +90,8 @@ def library():
         lib.lqr_solve_noalloc.argtypes = [P(LqrProblem), P(LqrOptions), _vp]
         lib.lqr_solve_noalloc.restype = ctypes.c_int
         lib.lqr_solve_phase.argtypes = [P(LqrProblem), P(LqrOptions), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+        lib.lqr_link_multipliers.restype = ctypes.c_int
+        lib.lqr_link_multipliers.argtypes = [P(LqrProblem), P(LqrOptions), ctypes.c_int32, _vp, _vp]
         lib.lqr_solve_phase.restype = ctypes.c_int
         lib.lqr_solve_batched.argtypes = [P(LqrProblem), ctypes.c_int32, P(LqrOptions), _vp,
                                           ctypes.c_size_t, _vp]
@@ -158,6 +160,12 @@ def lqr_solve_phase(prob: LqrProblem, opts: LqrOptions, phase: int, ws: int, ws_
     st = library().lqr_solve_phase(ctypes.byref(prob), ctypes.byref(opts), int(phase), ws, ws_bytes, stream)
     if st != SUCCESS:
         raise LQRError(st, "lqr_solve_phase")
+
+
+def lqr_link_multipliers(prob: LqrProblem, opts: LqrOptions, segments: int, mu: int, stream: int) -> None:
+    st = library().lqr_link_multipliers(ctypes.byref(prob), ctypes.byref(opts), int(segments), mu, stream)
+    if st != SUCCESS:
+        raise LQRError(st, "lqr_link_multipliers")
 
 
 def lqr_solve_batched(probs, batch: int, opts: LqrOptions, ws: int, ws_bytes: int, stream: int) -> None:
@@ -267,6 +275,22 @@ def solve(data: dict, segments: int = 0, precision: str = "fp64", algo: str = "p
     lqr_solve(prob, opts, ws.data_ptr(), ws.numel(), s)
     out["_workspace"] = ws
     return out
+
+
+def link_multipliers(data: dict, out: dict, segments: int = 0, precision: str = "fp64",
+                     algo: str = "parallel", stream=None):
+    """The link multipliers mu_j (J - 1 rows of n) of an instance solved by
+    ``solve`` with these arguments (its outputs P, p and x must be present).
+    ``segments`` 0 means the planner's choice, as in ``solve``."""
+    import torch
+    T, n, m = data["B"].shape
+    prob = _problem(data, out, segments)
+    opts = options(precision, algo)
+    J = int(segments) if segments else int(lqr_plan_segments(ctypes.byref(prob), 1, opts)[0][0])
+    mu = torch.empty(max(J - 1, 0), n, dtype=out["x"].dtype, device=out["x"].device)
+    s = (stream or torch.cuda.current_stream(out["x"].device)).cuda_stream
+    lqr_link_multipliers(prob, opts, J, mu.data_ptr() if J > 1 else 0, s)
+    return mu
 
 
 def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "parallel",

@@ -716,6 +716,24 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
   }
 }
 
+lqr_status_t lqr_link_multipliers(const lqr_problem_t* prob, const lqr_options_t* opts,
+                                  int32_t segments, void* mu, void* stream) {
+  try {
+    if (!prob) return LQR_ERR_INVALID_ARG;
+    lqr_status_t st = check_options(opts);
+    if (st != LQR_SUCCESS) return st;
+    if ((st = check_dims(*prob)) != LQR_SUCCESS) return st;
+    if (segments < 1 || segments > prob->T || prob->n > lqr::kBigMaxN) return LQR_ERR_INVALID_ARG;
+    if (segments == 1) return LQR_SUCCESS;
+    if (!prob->P || !prob->p || !prob->x || !mu) return LQR_ERR_INVALID_ARG;
+    const hipError_t e = lqr::launch_link_mu(prob->n, prob->T, segments, prob->P, prob->p, prob->x, mu,
+                                        is_f32(opts), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
+  } catch (...) {
+    return LQR_ERR_INVALID_ARG;
+  }
+}
+
 lqr_status_t lqr_plan_segments(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
                                int32_t* segments, double* est_us) {
   try {

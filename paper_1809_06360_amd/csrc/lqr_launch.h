@@ -100,6 +100,9 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream);
 // First launch of the logarithmic-depth linking solve: scan buffer 0 from the
 // phase-1 summaries and the last segment's value (k_link_tree.hip).
 hipError_t launch_link_init(const InstDesc& d, hipStream_t stream);
+// mu_j = P x + p at the J - 1 link points of a solved instance (its outputs).
+hipError_t launch_link_mu(int n, int T, int J, const void* P, const void* p, const void* x, void* mu,
+                          bool f32, hipStream_t stream);
 
 // Large-state path (65..128 states, big_device.h): the sweep kernels of
 // engine eng (1: FP64, 2: FP32 matrix cores) -- kind 1 phase 1, kind 3 phase 3

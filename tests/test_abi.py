@@ -259,3 +259,27 @@ def test_workspace_plan_regions_are_disjoint(dims):
                 regions = (a0, a1, f0, f1, lay["scratch_off"])
                 assert seen is None or regions == seen, (prec, algo, phased)
                 seen = regions
+
+
+def test_link_multipliers_checks_its_arguments_on_the_host():
+    """lqr_link_multipliers rejects a segment count outside 1..T, missing
+    outputs and n above 128 before it touches the device, and J = 1 (no link
+    point) is a no-op."""
+    prob = _prob(4, 2, 8, 2)
+    L.lqr_link_multipliers(prob, L.options(), 1, None, 0)        # nothing to write
+    for J in (0, 9):
+        with pytest.raises(L.LQRError) as e:
+            L.lqr_link_multipliers(prob, L.options(), J, 256, 0)
+        assert e.value.status == L.ERR_INVALID_ARG
+    with pytest.raises(L.LQRError) as e:                      # P, p, x are NULL
+        L.lqr_link_multipliers(prob, L.options(), 2, 256, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    prob.P = prob.p = prob.x = 256
+    with pytest.raises(L.LQRError) as e:                      # no output array
+        L.lqr_link_multipliers(prob, L.options(), 2, None, 0)
+    assert e.value.status == L.ERR_INVALID_ARG
+    big = _prob(129, 2, 8, 2)
+    big.P = big.p = big.x = 256
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_link_multipliers(big, L.options(), 2, 256, 0)
+    assert e.value.status == L.ERR_INVALID_ARG

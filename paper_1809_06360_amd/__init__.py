@@ -310,7 +310,9 @@ def solve_batched(datas, segments=None, precision: str = "fp64", algo: str = "pa
         n, m, T = _validate(data, dtype, device)
         out = outputs[i] if outputs is not None else _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol)
         outs.append(out)
-        arr[i] = _problem(data, out, 0 if segments is None else segments[i])
+        # the segment count is part of the workspace layout: backward() reuses it
+        out["_segments"] = 0 if segments is None else int(segments[i])
+        arr[i] = _problem(data, out, out["_segments"])
     opts = options(precision, algo, phased)
     nbytes = lqr_workspace_size(arr, batch, opts)
     ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
@@ -341,7 +343,7 @@ def backward(datas, outs, dl_dx, dl_du, which=GRAD_KEYS, workspace=None, stream=
             if out.get(key) is None:
                 raise ValueError("backward needs the forward output %r (solve with with_lam=True, "
                                  "with_chol=True)" % key)
-        probs[i] = _problem(data, out, 0)
+        probs[i] = _problem(data, out, out.get("_segments", 0))
         z = lambda *s: torch.empty(*s, dtype=data["A"].dtype, device=data["A"].device)  # noqa: E731
         shapes = dict(A=(T, n, n), B=(T, n, m), c=(T, n), Q=(T + 1, n, n), q=(T + 1, n),
                       R=(T, m, m), r=(T, m), S=(T, m, n), x0=(n,))

@@ -12,11 +12,11 @@
 namespace lqr {
 namespace cost {
 
-constexpr double kDual[2][4] = {{9.7286, 0.730256, 0.429983, 0}, {0, 0.356084, 0.357421, 1.40153}};
-constexpr double kDualStreamed[2][4] = {{0, 0, 0, 0}, {18.2212, 0.670574, 0.102654, 0.879499}};
-constexpr double kPlain[2][4] = {{7.14759, 0.647563, 0.327282, 0}, {0, 0.56655, 0.11784, 1.3803}};
-constexpr double kRoll[2][4] = {{3.00464, 0.00973967, 0, 0}, {2.82051, 0, 0.00239331, 0.297841}};
-constexpr double kLink[2][4] = {{4.32689, 1.86254, 0, 6.81954}, {46.8948, 0, 0, 10.0985}};
+constexpr double kDual[2][4] = {{9.94823, 0.753842, 0.434153, 0}, {0, 0.406604, 0.3238, 1.45567}};
+constexpr double kDualStreamed[2][4] = {{0, 0, 0, 0}, {15.0186, 0.76935, 0.121546, 0.896429}};
+constexpr double kPlain[2][4] = {{7.13742, 0.669526, 0.32809, 0}, {0.200634, 0.587989, 0.106433, 1.43635}};
+constexpr double kRoll[2][4] = {{3.13653, 0.00860262, 0, 0}, {2.90969, 0, 0, 0.303048}};
+constexpr double kLink[2][4] = {{5.17158, 0.883042, 0, 0}, {0, 0.39376, 1.30191, 0}};
 constexpr double kTask = 3.0;
 
 }  // namespace cost

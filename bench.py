@@ -324,8 +324,9 @@ def run_single(args, key, steps, warmup, serial_steps, cpu_seconds, with_mixed_l
            "frac_fp64_peak_executed": flops[2] / (kern_ms[2] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
            "precision": "fp64"}
     if uses_scan(n, J):
-        ph2["kernels"] = ("k_link_init, %d x %s, %s, %s" % (
-            max(1, (J - 1).bit_length()), "k_big_link_combine" if big else "k_link_combine",
+        ph2["kernels"] = ("%s%d x %s, %s, %s" % (
+            "k_link_init, " if big else "", max(1, (J - 1).bit_length()),
+            "k_big_link_combine" if big else "k_link_combine",
             "k_big_link_maps" if big else "k_link_maps", "k_big_link_forward" if big else "k_link_forward"))
     roofline["phase2_sequence"] = ph2
 

@@ -662,22 +662,71 @@ LQR_DEV int wg_invert(const double* A, int lda, int n, double* Ainv, int ldi, In
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((vector_size(32)));
 
-// One operand stream of a tile: kc consecutive k-steps (4 k each) of A and B
-// fragments loaded up front (independent LDS reads), then kc MFMAs.
-template <bool TA, bool TB, int KC>
-LQR_DEV void mfma_chunk(f64x4& acc, const double* A, int lda, const double* B, int ldb, int M, int N,
-                        int K, int i, int j, int k0, int lk, double sgn) {
-  double a[KC], b[KC];
+// One operand stream of a pair of tiles (tile 1 only if `two`): per lane the
+// fragment addresses are formed once (rows and columns clamped into the
+// operands; out-of-range rows and columns only reach discarded outputs) and
+// walked by constant strides; the k range runs in chunks of 16 (four MFMAs per
+// tile) with the next chunk's fragments loaded before the current chunk's
+// MFMAs, and a last partial chunk whose out-of-range k are zeroed. NEG
+// subtracts the product.
+template <bool TA, bool TB, bool NEG>
+LQR_DEV void mfma_pair(f64x4& acc0, f64x4& acc1, bool two, const double* A, int lda, const double* B,
+                       int ldb, int M, int N, int K, int i0, int j0, int i1, int j1, int li, int lk) {
+  const int ra0 = min(i0 + li, M - 1), cb0 = min(j0 + li, N - 1);
+  const int ra1 = min(i1 + li, M - 1), cb1 = min(j1 + li, N - 1);
+  const int sa = TA ? 4 * lda : 4, sb = TB ? 4 : 4 * ldb;  // one k-step of 4
+  const double* pa0 = TA ? A + lk * lda + ra0 : A + ra0 * lda + lk;
+  const double* pa1 = TA ? A + lk * lda + ra1 : A + ra1 * lda + lk;
+  const double* pb0 = TB ? B + cb0 * ldb + lk : B + lk * ldb + cb0;
+  const double* pb1 = TB ? B + cb1 * ldb + lk : B + lk * ldb + cb1;
+  const int full = K >> 4;
+  double a0[4], b0[4], a1[4], b1[4];
+  auto load = [&](int c) {
 #pragma unroll
-  for (int s = 0; s < KC; ++s) {
-    const int k = k0 + 4 * s + lk;
-    const bool kin = k < K;
-    const int kk = kin ? k : K - 1;
-    a[s] = (kin && i < M) ? sgn * el<TA>(A, lda, i < M ? i : M - 1, kk) : 0.0;
-    b[s] = (kin && j < N) ? el<TB>(B, ldb, kk, j < N ? j : N - 1) : 0.0;
+    for (int s = 0; s < 4; ++s) {
+      a0[s] = pa0[(4 * c + s) * sa];
+      b0[s] = pb0[(4 * c + s) * sb];
+    }
+    if (two) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a1[s] = pa1[(4 * c + s) * sa];
+        b1[s] = pb1[(4 * c + s) * sb];
+      }
+    }
+  };
+  if (full > 0) load(0);
+  for (int c = 0; c < full; ++c) {
+    double x0[4], y0[4], x1[4], y1[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      x0[s] = a0[s];
+      y0[s] = b0[s];
+      x1[s] = a1[s];
+      y1[s] = b1[s];
+    }
+    if (c + 1 < full) load(c + 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -x0[s] : x0[s], y0[s], acc0, 0, 0, 0);
+      if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -x1[s] : x1[s], y1[s], acc1, 0, 0, 0);
+    }
   }
+  const int k0 = full << 4;
+  if (k0 < K) {
 #pragma unroll
-  for (int s = 0; s < KC; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * s + lk;
+      const bool kin = k < K;
+      const int st = ((kin ? k : K - 1) - lk) >> 2;  // clamped k-step of this lane's row
+      const double xa0 = kin ? pa0[st * sa] : 0.0, xb0 = kin ? pb0[st * sb] : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -xa0 : xa0, xb0, acc0, 0, 0, 0);
+      if (two) {
+        const double xa1 = kin ? pa1[st * sa] : 0.0, xb1 = kin ? pb1[st * sb] : 0.0;
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -xa1 : xa1, xb1, acc1, 0, 0, 0);
+      }
+    }
+  }
 }
 
 template <bool TA1, bool TB1, bool TA2, bool TB2, typename Epi, typename Skip = NoSkip>
@@ -685,33 +734,31 @@ LQR_DEV void mgemm_sub(int M, int N,
                        int K1, const double* A1, int lda1, const double* B1, int ldb1,
                        int K2, const double* A2, int lda2, const double* B2, int ldb2,
                        Epi epi, Skip skip = Skip()) {
-  constexpr int KC = 4;  // k-steps per preloaded chunk (16 k)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int tn = (N + 15) >> 4;
   const int tiles = ((M + 15) >> 4) * tn;
   for (int t0 = wave; t0 < tiles; t0 += 2 * kWaves) {
     const int t1 = t0 + kWaves;
-    const bool has1 = t1 < tiles;
-    const int i0a = (t0 / tn) << 4, j0a = (t0 % tn) << 4;
-    const int i0b = has1 ? (t1 / tn) << 4 : i0a, j0b = has1 ? (t1 % tn) << 4 : j0a;
-    const bool runa = !skip(i0a, j0a, 16, 16), runb = has1 && !skip(i0b, j0b, 16, 16);
+    int ia = (t0 / tn) << 4, ja = (t0 % tn) << 4;
+    int ib = t1 < tiles ? (t1 / tn) << 4 : ia, jb = t1 < tiles ? (t1 % tn) << 4 : ja;
+    bool runa = !skip(ia, ja, 16, 16);
+    bool runb = t1 < tiles && !skip(ib, jb, 16, 16);
     if (!runa && !runb) continue;
+    if (!runa) {  // only the second tile: compute it in the first slot
+      ia = ib;
+      ja = jb;
+      runa = true;
+      runb = false;
+    }
     f64x4 acca = {0.0, 0.0, 0.0, 0.0}, accb = {0.0, 0.0, 0.0, 0.0};
-    const int ia = i0a + li, ja = j0a + li, ib = i0b + li, jb = j0b + li;
-    for (int k0 = 0; k0 < K1; k0 += 4 * KC) {
-      mfma_chunk<TA1, TB1, KC>(acca, A1, lda1, B1, ldb1, M, N, K1, ia, ja, k0, lk, 1.0);
-      if (has1) mfma_chunk<TA1, TB1, KC>(accb, A1, lda1, B1, ldb1, M, N, K1, ib, jb, k0, lk, 1.0);
-    }
-    for (int k0 = 0; k0 < K2; k0 += 4 * KC) {
-      mfma_chunk<TA2, TB2, KC>(acca, A2, lda2, B2, ldb2, M, N, K2, ia, ja, k0, lk, -1.0);
-      if (has1) mfma_chunk<TA2, TB2, KC>(accb, A2, lda2, B2, ldb2, M, N, K2, ib, jb, k0, lk, -1.0);
-    }
+    if (K1 > 0) mfma_pair<TA1, TB1, false>(acca, accb, runb, A1, lda1, B1, ldb1, M, N, K1, ia, ja, ib, jb, li, lk);
+    if (K2 > 0) mfma_pair<TA2, TB2, true>(acca, accb, runb, A2, lda2, B2, ldb2, M, N, K2, ia, ja, ib, jb, li, lk);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = lk + 4 * r;
-      if (runa && i0a + i < M && j0a + li < N) epi(i0a + i, j0a + li, acca[r]);
-      if (runb && i0b + i < M && j0b + li < N) epi(i0b + i, j0b + li, accb[r]);
+      if (ia + i < M && ja + li < N) epi(ia + i, ja + li, acca[r]);
+      if (runb && ib + i < M && jb + li < N) epi(ib + i, jb + li, accb[r]);
     }
   }
 }

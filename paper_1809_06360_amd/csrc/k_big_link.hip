@@ -153,38 +153,44 @@ __global__ __launch_bounds__(kBT) void k_big_link_maps(InstDesc d, const double*
 
 // Boundary states x_{t_{j+1}} = F_j x_{t_j} + f_j from x_{t_0} = x0, then the
 // instance's info word. Thread t keeps a quarter row of F_j in registers
-// (row t/4, columns 32 (t%4) ..) and loads that of F_{j+1} while step j runs;
-// F is column-major, so 16 consecutive rows of a column are one load.
+// (row t/4, columns 32 (t%4) ..) and loads that of F_{j+1} (and f_{j+1}) while
+// step j runs; F is column-major, so 16 consecutive rows of a column are one
+// load; the four quarter sums meet by quad permutations.
 __global__ __launch_bounds__(kBT) void k_big_link_forward(InstDesc d) {
   extern __shared__ double smem[];
   const int n = d.n, J = d.J, nn = n * n;
   const int t = threadIdx.x, r = t >> 2, q = t & 3, c0 = 32 * q;
-  double* sx = smem;  // two state buffers of 128
-  for (int i = t; i < n; i += kBT) {
-    sx[i] = d.x0[i];
-    ws_bnd(d.ws, n, J, 0)[nn + n + i] = d.x0[i];
+  double* sx = smem;  // two state buffers of 128; entries past n stay zero
+  for (int i = t; i < 256; i += kBT) {
+    const double v = (i & 127) < n && i < 128 ? d.x0[i] : 0.0;
+    sx[i] = v;
+    if (i < n) ws_bnd(d.ws, n, J, 0)[nn + n + i] = v;
   }
-  double cur[32], nxt[32];
-  auto fetch = [&](double (&dst)[32], int jj) {
+  // F_jj's quarter row and f_jj's entry of this thread; columns past n load a
+  // clamped (finite) element that meets a zero state entry, so no load or
+  // product is conditional
+  double cur[32], nxt[32], fc = 0.0, fnx = 0.0;
+  const int rr = r < n ? r : 0;
+  auto fetch = [&](double (&dst)[32], double& fv, int jj) {
     const double* F = ws_link(d.ws, n, J, jj);
-    const bool ok = r < n;
-    const double* row = F + (ok ? r : 0);
 #pragma unroll
-    for (int c = 0; c < 32; ++c) dst[c] = (ok && c0 + c < n) ? row[(size_t)(c0 + c) * n] : 0.0;
+    for (int c = 0; c < 32; ++c) dst[c] = F[(size_t)min(c0 + c, n - 1) * n + rr];
+    fv = F[nn + rr];
   };
-  if (J > 1) fetch(cur, 0);
+  if (J > 1) fetch(cur, fc, 0);
   __syncthreads();
   int b = 0;
   for (int j = 0; j < J - 1; ++j) {
-    if (j + 1 < J - 1) fetch(nxt, j + 1);
-    const double* x = sx + b * 128;
-    double acc = 0.0;
+    if (j + 1 < J - 1) fetch(nxt, fnx, j + 1);
+    const double* x = sx + b * 128 + c0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 32; ++c) acc = fma(cur[c], (c0 + c < n) ? x[c0 + c] : 0.0, acc);
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
+    for (int c = 0; c < 32; ++c) acc[c & 3] = fma(cur[c], x[c], acc[c & 3]);
+    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    s += quad_xor<0xB1>(s);  // the four quarter rows of row r
+    s += quad_xor<0x4E>(s);
     if (q == 0 && r < n) {
-      const double v = acc + ws_link(d.ws, n, J, j)[nn + r];
+      const double v = s + fc;
       sx[(1 - b) * 128 + r] = v;
       ws_bnd(d.ws, n, J, j + 1)[nn + n + r] = v;
     }
@@ -192,6 +198,7 @@ __global__ __launch_bounds__(kBT) void k_big_link_forward(InstDesc d) {
     b = 1 - b;
 #pragma unroll
     for (int c = 0; c < 32; ++c) cur[c] = nxt[c];
+    fc = fnx;
   }
   if (t == 0) {
     int f = 0;

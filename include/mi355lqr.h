@@ -149,11 +149,25 @@ typedef struct {
 #define LQR_FLAG_PHASED 0x1u   /* lqr_solve_batched: run the parallel algorithm as three
                                   launches, one per phase, instead of one persistent
                                   launch (same results; for comparison and timing) */
+#define LQR_FLAG_SMOOTHED 0x2u /* lqr_solve, lqr_solve_phase, lqr_solve_noalloc with
+                                  LQR_ALGO_PARALLEL, n <= 64: output the paper's smoothed
+                                  policies (Sec. III-A) instead of the serial-exact ones.
+                                  Segment j < J-2 is re-solved from segment j+1's
+                                  cost-to-go at its start with that segment's end fixed at
+                                  its link point, 1/2 x'(P0 + Gam Psi^{-1} Gam')x +
+                                  (pbar + Gam Psi^{-1}(psi - x_link))'x; segment J-2 from
+                                  the exact value. K, k, P, p are the smoothed policies and
+                                  values; x and u are still the optimal trajectory. Every
+                                  inner segment must reach any link point (Psi invertible;
+                                  otherwise info LQR_INFO_COUPLING + j). Rejected with
+                                  LQR_ERR_INVALID_ARG under LQR_ALGO_SERIAL and
+                                  LQR_ERR_UNSUPPORTED for batched and adjoint calls and
+                                  n above 64. */
 
 typedef struct {
     lqr_precision_t precision;
     lqr_algo_t algo;
-    uint32_t flags;        /* 0 or LQR_FLAG_PHASED; other bits are invalid */
+    uint32_t flags;        /* LQR_FLAG_PHASED, LQR_FLAG_SMOOTHED or 0; other bits are invalid */
 } lqr_options_t;
 
 /* Upstream gradients and gradient outputs of lqr_backward (device pointers). */

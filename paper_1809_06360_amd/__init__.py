@@ -21,7 +21,8 @@ __all__ = [
     "lqr_solve_noalloc", "lqr_solve_phase", "lqr_solve_batched", "lqr_backward", "lqr_status_string",
     "solve", "solve_batched", "plan_segments", "backward", "LQRError",
     "SUCCESS", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "ALGO_PARALLEL", "ALGO_SERIAL",
-    "INFO_COUPLING", "INFO_QUEUE", "INFO_NONFINITE", "FLAG_PHASED",
+    "INFO_COUPLING", "INFO_QUEUE", "INFO_NONFINITE", "FLAG_PHASED", "FLAG_SMOOTHED",
+    "link_multipliers",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmi355lqr.so")
@@ -34,6 +35,7 @@ INFO_COUPLING = 0x40000000
 INFO_QUEUE = 0x20000000
 INFO_NONFINITE = -1
 FLAG_PHASED = 0x1
+FLAG_SMOOTHED = 0x2
 
 _vp = ctypes.c_void_p
 
@@ -188,8 +190,10 @@ _ALGO = {"parallel": ALGO_PARALLEL, "serial": ALGO_SERIAL}
 INPUTS = ("A", "B", "c", "Q", "q", "R", "r", "x0")
 
 
-def options(precision: str = "fp64", algo: str = "parallel", phased: bool = False) -> LqrOptions:
-    return LqrOptions(_PREC[precision], _ALGO[algo], FLAG_PHASED if phased else 0)
+def options(precision: str = "fp64", algo: str = "parallel", phased: bool = False,
+            smoothed: bool = False) -> LqrOptions:
+    return LqrOptions(_PREC[precision], _ALGO[algo],
+                      (FLAG_PHASED if phased else 0) | (FLAG_SMOOTHED if smoothed else 0))
 
 
 def plan_segments(dims, segments=None, algo: str = "parallel"):
@@ -258,17 +262,19 @@ def _workspace(nbytes, device):
 
 def solve(data: dict, segments: int = 0, precision: str = "fp64", algo: str = "parallel",
           with_P: bool = True, with_lam: bool = True, with_chol: bool = False,
-          workspace=None, stream=None) -> dict:
+          workspace=None, stream=None, smoothed: bool = False) -> dict:
     """Solve one LQR instance given as a dict of device tensors (A, B, c, Q, q,
     R, r, x0 and optionally S; float64). Returns a dict of output tensors
-    (K, k, P, p, x, u, lam, chol, info). Asynchronous on the current stream."""
+    (K, k, P, p, x, u, lam, chol, info). Asynchronous on the current stream.
+    ``smoothed``: the paper's smoothed policies instead of the serial-exact
+    ones (LQR_FLAG_SMOOTHED)."""
     import torch
     dtype = torch.float32 if precision == "fp32" else torch.float64
     device = data["A"].device
     n, m, T = _validate(data, dtype, device)
     out = _outputs(n, m, T, dtype, device, with_P, with_lam, with_chol)
     prob = _problem(data, out, segments)
-    opts = options(precision, algo)
+    opts = options(precision, algo, smoothed=smoothed)
     nbytes = lqr_workspace_size(ctypes.byref(prob), 1, opts)
     ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
     s = (stream or torch.cuda.current_stream(device)).cuda_stream

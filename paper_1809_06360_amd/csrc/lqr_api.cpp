@@ -120,6 +120,7 @@ struct BatchPlan {
 
 bool is_serial(const lqr_options_t* o) { return o && o->algo == LQR_ALGO_SERIAL; }
 bool is_phased(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_PHASED); }
+bool is_smoothed(const lqr_options_t* o) { return o && (o->flags & LQR_FLAG_SMOOTHED); }
 bool is_mixed(const lqr_options_t* o) { return o && o->precision == LQR_PREC_MIXED; }
 bool is_f32(const lqr_options_t* o) { return o && o->precision == LQR_PREC_FP32; }
 // Product engine of the large-state kernels: FP32 matrix cores in the mixed and
@@ -128,7 +129,8 @@ int big_engine(const lqr_options_t* o) { return (is_mixed(o) || is_f32(o)) ? 2 :
 
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
-  if (o->flags & ~(uint32_t)LQR_FLAG_PHASED) return LQR_ERR_INVALID_ARG;
+  if (o->flags & ~(uint32_t)(LQR_FLAG_PHASED | LQR_FLAG_SMOOTHED)) return LQR_ERR_INVALID_ARG;
+  if ((o->flags & LQR_FLAG_SMOOTHED) && o->algo == LQR_ALGO_SERIAL) return LQR_ERR_INVALID_ARG;
   if (o->algo != LQR_ALGO_PARALLEL && o->algo != LQR_ALGO_SERIAL) return LQR_ERR_INVALID_ARG;
   if (o->precision != LQR_PREC_FP64 && o->precision != LQR_PREC_MIXED &&
       o->precision != LQR_PREC_FP32)
@@ -568,6 +570,7 @@ lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, 
   if ((st = check_device(plan)) != LQR_SUCCESS) return st;
   if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return LQR_ERR_INVALID_ARG;
+  if (is_smoothed(opts) && plan.big) return LQR_ERR_UNSUPPORTED;
   forget_other_layouts(ws, layout_key(prob, 1));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int eng = launch_engine(plan.max_n, is_mixed(opts) || is_f32(opts));
@@ -591,8 +594,16 @@ lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, 
         if (e == hipSuccess) e = launch_big_sweep(d, 3, beng, plan.lds3, s);
       }
     } else {
-      e = is_serial(opts) ? launch_serial(d, plan.lds_serial, eng, s)
-                          : launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+      if (is_serial(opts)) {
+        e = launch_serial(d, plan.lds_serial, eng, s);
+      } else if (is_smoothed(opts)) {
+        e = launch_phase(d, 1, plan.lds1, eng, s);
+        if (e == hipSuccess) e = launch_phase(d, 2, plan.lds2, eng, s);
+        if (e == hipSuccess) e = launch_smooth_seed(d, plan.lds2, s);
+        if (e == hipSuccess) e = launch_phase(d, 3, plan.lds3, eng, s);
+      } else {
+        e = launch_parallel(d, plan.lds1, plan.lds2, plan.lds3, eng, s);
+      }
     }
   }
   if (e == hipSuccess) e = launch_convert_list(cout, s);
@@ -686,6 +697,7 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
     BatchPlan plan;
     lqr_status_t st = make_plan(prob, 1, opts, &plan);
     if (st != LQR_SUCCESS) return st;
+    if (is_smoothed(opts) && plan.big) return LQR_ERR_UNSUPPORTED;
     if ((st = check_pointers(*prob)) != LQR_SUCCESS) return st;
     if ((st = check_device(plan)) != LQR_SUCCESS) return st;
     if (!ws || ws_bytes < plan.total_bytes) return LQR_ERR_WORKSPACE;
@@ -709,6 +721,7 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
     } else {
       const size_t lds = phase == 1 ? plan.lds1 : phase == 2 ? plan.lds2 : plan.lds3;
       e = launch_phase(d, phase, lds, eng, s);
+      if (e == hipSuccess && phase == 2 && is_smoothed(opts)) e = launch_smooth_seed(d, plan.lds2, s);
     }
     return e == hipSuccess ? LQR_SUCCESS : LQR_ERR_HIP;
   } catch (...) {
@@ -752,6 +765,7 @@ lqr_status_t lqr_plan_segments(const lqr_problem_t* probs, int32_t batch, const 
 lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const lqr_options_t* opts,
                                void* ws, size_t ws_bytes, void* stream) {
   try {
+    if (is_smoothed(opts) && check_options(opts) == LQR_SUCCESS) return LQR_ERR_UNSUPPORTED;
     BatchPlan plan;
     lqr_status_t st = make_plan(probs, batch, opts, &plan);
     if (st != LQR_SUCCESS) return st;
@@ -841,6 +855,7 @@ lqr_status_t lqr_backward(const lqr_problem_t* probs, int32_t batch, const lqr_g
   try {
     lqr_status_t st = check_options(opts);
     if (st != LQR_SUCCESS) return st;
+    if (is_smoothed(opts)) return LQR_ERR_UNSUPPORTED;
     if (!grads) return LQR_ERR_INVALID_ARG;
     AdjPlan ap;
     const bool f32 = is_f32(opts);

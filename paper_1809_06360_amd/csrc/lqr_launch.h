@@ -100,6 +100,9 @@ hipError_t launch_link_tree(const InstDesc& d, size_t lds, hipStream_t stream);
 // First launch of the logarithmic-depth linking solve: scan buffer 0 from the
 // phase-1 summaries and the last segment's value (k_link_tree.hip).
 hipError_t launch_link_init(const InstDesc& d, hipStream_t stream);
+// Smoothed-policy seeds: the boundary values of segments 1..J-2 replaced by
+// those segments' cost-to-go with their ends fixed at the link points.
+hipError_t launch_smooth_seed(const InstDesc& d, size_t lds, hipStream_t stream);
 // mu_j = P x + p at the J - 1 link points of a solved instance (its outputs).
 hipError_t launch_link_mu(int n, int T, int J, const void* P, const void* p, const void* x, void* mu,
                           bool f32, hipStream_t stream);

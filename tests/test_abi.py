@@ -80,10 +80,15 @@ def test_workspace_size_rejects_bad_dimensions(n, m, T, J):
 
 def test_workspace_size_rejects_bad_options():
     opts = L.options()
-    opts.flags = 2          # only LQR_FLAG_PHASED (1) is defined
+    opts.flags = 4          # only LQR_FLAG_PHASED (1) and LQR_FLAG_SMOOTHED (2) are defined
     with pytest.raises(L.LQRError) as e:
         L.lqr_workspace_size(ctypes.byref(_prob()), 1, opts)
     assert e.value.status == L.ERR_INVALID_ARG
+    with pytest.raises(L.LQRError) as e:     # smoothing needs the segmented algorithm
+        L.lqr_workspace_size(ctypes.byref(_prob()), 1, L.options(algo="serial", smoothed=True))
+    assert e.value.status == L.ERR_INVALID_ARG
+    assert L.lqr_workspace_size(ctypes.byref(_prob()), 1, L.options(smoothed=True)) == \
+        L.lqr_workspace_size(ctypes.byref(_prob()), 1, L.options())
     with pytest.raises(L.LQRError):
         L.lqr_workspace_size(ctypes.byref(_prob()), 0, L.options())
 
@@ -283,3 +288,16 @@ def test_link_multipliers_checks_its_arguments_on_the_host():
     with pytest.raises(L.LQRError) as e:
         L.lqr_link_multipliers(big, L.options(), 2, 256, 0)
     assert e.value.status == L.ERR_INVALID_ARG
+
+
+def test_smoothed_policies_are_refused_where_they_are_not_built():
+    """LQR_FLAG_SMOOTHED is rejected by the batched and adjoint calls before
+    they touch the device."""
+    arr = (L.LqrProblem * 1)(_prob(4, 2, 8, 2))
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_solve_batched(arr, 1, L.options(smoothed=True), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_UNSUPPORTED
+    grads = (L.LqrGrad * 1)()
+    with pytest.raises(L.LQRError) as e:
+        L.lqr_backward(arr, 1, grads, L.options(smoothed=True), 256, 1 << 20, 0)
+    assert e.value.status == L.ERR_UNSUPPORTED

@@ -1,0 +1,287 @@
+// Plain Riccati recursion (Sec. II, eqs. Kx, k1, update:Vxx, update:vx) for
+// instances with n <= 16 and m <= 16, one 256-thread workgroup per instance.
+//
+// At these sizes a stage is a few thousand multiply-adds and the general sweep
+// is bound by latency: global loads on the dependency chain and barriers per
+// pivot. Here every block lives in LDS padded to 16 x 16 with zeros, so that
+// thread (i, j) = (tid / 16, tid % 16) owns one element of each 16 x 16
+// product and no loop depends on n or m; the next stage's inputs are loaded
+// into registers at the top of a stage and stored to the other half of a
+// double buffer at its end, so their latency overlaps the stage's work. A
+// stage costs four barriers:
+//   1. Y = P A, W = P B, g = P c + p                      (all threads)
+//   2. H = R + B'W, Hux = S + B'Y, h = r + B'g            (all threads)
+//   3. H = L_unit D L_unit', [K | k] = -H^{-1}[Hux | h]   (wave 0, see below)
+//      and meanwhile Q + A'Y, q + A'g                     (waves 1-3)
+//   4. P <- (Q + A'Y) + Hux'K, p <- (q + A'g) + Hux'k     (all threads)
+// Loops carry no lane-dependent branches (every thread runs the same dot
+// products and only the stores are conditional), so no LDS wait lands inside
+// a loop. Thread (i, j) of a symmetric result computes element
+// (max(i, j), min(i, j)) in a fixed order, so both halves are bitwise equal.
+// The rollout (x, u, costates) is the general one.
+#include "lqr_device.h"
+#include "lqr_kernels.h"
+#include "lqr_launch.h"
+
+namespace lqr {
+
+namespace {
+
+constexpr int kS = 16;            // padded block edge
+constexpr int kB = kS * kS;       // padded block size
+// one half of the stage-input double buffer: A | B | S | Q | R | c | q | r
+constexpr int kStageDoubles = 5 * kB + 3 * kS;
+// LDS carve (doubles): 2 stage buffers, then P | p | Y | W | g | H | Hux | h |
+// K | kv | Lu | Pa | pa | D | zero | Col[2], then an int flag
+constexpr int kSmallDoubles = 2 * kStageDoubles + 8 * kB + 11 * kS;
+
+struct StageRegs {
+  double a, b, s, q2, r2, v;  // this thread's element of A, B, S, Q, R; of c, q or r
+};
+
+// This thread's share of stage t's inputs (zero outside the instance's sizes).
+LQR_DEV StageRegs fetch_stage(const InstDesc& d, int t, int i, int j) {
+  const int n = d.n, m = d.m;
+  StageRegs g;
+  g.a = (i < n && j < n) ? gp(d.A)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.b = (i < n && j < m) ? gp(d.B)[(size_t)t * n * m + i * m + j] : 0.0;
+  g.s = (d.S && i < m && j < n) ? gp(d.S)[(size_t)t * m * n + i * n + j] : 0.0;
+  g.q2 = (i < n && j < n) ? gp(d.Q)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.r2 = (i < m && j < m) ? gp(d.R)[(size_t)t * m * m + i * m + j] : 0.0;
+  g.v = 0.0;
+  if (j == 0 && i < n) g.v = gp(d.c)[(size_t)t * n + i];
+  if (j == 1 && i < n) g.v = gp(d.q)[(size_t)t * n + i];
+  if (j == 2 && i < m) g.v = gp(d.r)[(size_t)t * m + i];
+  return g;
+}
+
+LQR_DEV void store_stage(double* buf, const StageRegs& g, int i, int j) {
+  const int e = i * kS + j;
+  buf[e] = g.a;
+  buf[kB + e] = g.b;
+  buf[2 * kB + e] = g.s;
+  buf[3 * kB + e] = g.q2;
+  buf[4 * kB + e] = g.r2;
+  if (j < 3) buf[5 * kB + j * kS + i] = g.v;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs) {
+  extern __shared__ double smem[];
+  const InstDesc d = descs ? descs[blockIdx.x] : single;
+  const int n = d.n, m = d.m, T = d.T;
+  const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
+  double* sP = smem + 2 * kStageDoubles;
+  double* sp = sP + kB;
+  double* sY = sp + kS;
+  double* sW = sY + kB;
+  double* sg = sW + kB;
+  double* sH = sg + kS;
+  double* sHux = sH + kB;
+  double* sh = sHux + kB;
+  double* sK = sh + kS;
+  double* skv = sK + kB;
+  double* sLu = skv + kS;     // unit lower factor of H (row-major, below the diagonal)
+  double* sPa = sLu + kB;     // Q + A'Y
+  double* spa = sPa + kB;     // q + A'g
+  double* sD = spa + kS;      // pivots of H, then their square roots
+  double* sZero = sD + kS;    // 16 zeros
+  double* sCol = sZero + kS;  // [2][16]: the pivot column published in a round
+  int* flags = reinterpret_cast<int*>(sCol + 2 * kS);  // [0]: non-finite value gradient
+  const int mx = i > j ? i : j, mn = i > j ? j : i;
+
+  write_terminal(d);
+  // value at T, the last stage's inputs, zero gains (rows >= m stay zero)
+  sP[tid] = (i < n && j < n) ? gp(d.Q)[(size_t)T * n * n + i * n + j] : 0.0;
+  if (tid < kS) sp[tid] = tid < n ? gp(d.q)[(size_t)T * n + tid] : 0.0;
+  sK[tid] = 0.0;
+  if (tid < kS) {
+    skv[tid] = 0.0;
+    sZero[tid] = 0.0;
+  }
+  if (tid == 0) flags[0] = 0;
+  store_stage(smem, fetch_stage(d, T - 1, i, j), i, j);
+  __syncthreads();
+
+  int fail = 0;  // wave 0's status (note_pivot)
+  for (int t = T - 1, cur = 0; t >= 0; --t, cur ^= 1) {
+    const double* bA = smem + cur * kStageDoubles;
+    const double* bB = bA + kB;
+    const double* bS = bA + 2 * kB;
+    const double* bQ = bA + 3 * kB;
+    const double* bR = bA + 4 * kB;
+    const double* bc = bA + 5 * kB;
+    const double* bq = bc + kS;
+    const double* br = bq + kS;
+    const StageRegs next = fetch_stage(d, t > 0 ? t - 1 : 0, i, j);
+
+    // 1. Y = P A, W = P B, g = P c + p
+    {
+      double y = 0.0, w = 0.0, gc = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kS; ++l) {
+        const double pil = sP[i * kS + l];
+        y = fma(pil, bA[l * kS + j], y);
+        w = fma(pil, bB[l * kS + j], w);
+        gc = fma(pil, bc[l], gc);
+      }
+      sY[tid] = y;
+      sW[tid] = w;
+      if (j == 0) sg[i] = gc + sp[i];
+    }
+    __syncthreads();
+
+    // 2. H = R + B'W (symmetrised R), Hux = S + B'Y, h = r + B'g
+    {
+      double hh = 0.5 * (bR[i * kS + j] + bR[j * kS + i]), hx = bS[tid], hv = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kS; ++l) {
+        const double bli = bB[l * kS + i];
+        hh = fma(bli, sW[l * kS + j], hh);
+        hx = fma(bli, sY[l * kS + j], hx);
+        hv = fma(bli, sg[l], hv);
+      }
+      sH[tid] = hh;
+      sHux[tid] = hx;
+      if (j == 0) sh[i] = br[i] + hv;
+    }
+    __syncthreads();
+
+    // 3. Wave 0: lane c < m holds column c of H, lane m + c (c < n) column c
+    //    of Hux, lane m + n the vector h, other lanes zeros; rows >= m are
+    //    zero and stay zero. Round k: lane k publishes its column in LDS
+    //    (pivot d_k = H(k, k) and H(r, k), r > k), and every lane updates its
+    //    column, v_r -= H(r, k) (v_k / d_k) for r > k. The trailing block stays
+    //    symmetric, so lane c > k's v_k / d_k is the unit lower factor's entry
+    //    (c, k), kept in Lu, and v_k / d_k is also the right-hand side's entry
+    //    of D^{-1} L_unit^{-1} [Hux | h]. Back substitution with L_unit' then
+    //    gives H^{-1}[Hux | h] = -[K | k], left in LDS (rows >= m zero); the
+    //    square roots of the pivots for the Cholesky factor L = L_unit D^{1/2}
+    //    go to D. Step 4 writes K, k and L to global memory.
+    if (tid < 64) {
+      const int c = tid;
+      const bool rcol = c >= m && c < m + n, vcol = c == m + n;
+      const double* col = c < m ? sH + c : rcol ? sHux + (c - m) : vcol ? sh : sZero;
+      const int cs = (c < m || rcol) ? kS : 1;
+      double v[kS];
+      static_for<0, kS>([&](auto R) { v[decltype(R)::value] = col[decltype(R)::value * cs]; });
+      int bad = 0;
+      static_for<0, kS>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        if (k < m) {
+          double* pub = sCol + (k & 1) * kS;  // alternate halves across rounds
+          if (c == k) {
+            static_for<k, kS>([&](auto R) { pub[decltype(R)::value] = v[decltype(R)::value]; });
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          double dk = pub[k];
+          if (!(dk > 0.0) || !isfinite(dk)) {
+            if (!bad) bad = isfinite(dk) ? 1 : 2;
+            dk = __builtin_nan("");
+          }
+          const double tk = v[k] * recip(dk);
+          if (c > k && c < m) sLu[c * kS + k] = tk;
+          if (c == 0) sD[k] = dk;
+          static_for<k + 1, kS>([&](auto I) {
+            constexpr int r = decltype(I)::value;
+            v[r] = fma(-pub[r], tk, v[r]);
+          });
+          v[k] = tk;
+        }
+      });
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // L_unit' x = y from the last row up
+      static_for<1, kS>([&](auto Ic) {
+        constexpr int r = kS - decltype(Ic)::value;  // kS-1 .. 1
+        if (r < m) {
+          const double xr = v[r];
+          static_for<0, r>([&](auto Kc) {
+            constexpr int k = decltype(Kc)::value;
+            v[k] = fma(-sLu[r * kS + k], xr, v[k]);
+          });
+        }
+      });
+      if (rcol) {
+        static_for<0, kS>([&](auto Kc) { sK[decltype(Kc)::value * kS + (c - m)] = -v[decltype(Kc)::value]; });
+      } else if (vcol) {
+        static_for<0, kS>([&](auto Kc) { skv[decltype(Kc)::value] = -v[decltype(Kc)::value]; });
+      }
+      fail = note_pivot(fail, bad, t);
+      if (c < m) sD[c] = sqrt(sD[c]);
+    } else {
+      // waves 1-3: the parts of the new value that do not need the gains
+      for (int e = tid - 64; e < kB; e += kThreads - 64) {
+        const int ei = e >> 4, ej = e & 15;
+        const int ex = ei > ej ? ei : ej, en = ei > ej ? ej : ei;
+        double v = 0.5 * (bQ[ei * kS + ej] + bQ[ej * kS + ei]);
+#pragma unroll 8
+        for (int l = 0; l < kS; ++l) v = fma(bA[l * kS + ex], sY[l * kS + en], v);
+        sPa[e] = v;
+      }
+      if (tid < 64 + kS) {
+        const int r = tid - 64;
+        double v = bq[r];
+#pragma unroll 8
+        for (int l = 0; l < kS; ++l) v = fma(bA[l * kS + r], sg[l], v);
+        spa[r] = v;
+      }
+    }
+    __syncthreads();
+
+    // 4. P <- (Q + A'Y) + Hux'K, p <- (q + A'g) + Hux'k; the next stage's
+    //    inputs go to the other buffer
+    {
+      double v = sPa[mx * kS + mn];
+#pragma unroll 8
+      for (int l = 0; l < kS; ++l) v = fma(sHux[l * kS + mx], sK[l * kS + mn], v);
+      sP[tid] = v;
+      if (d.P && i < n && j < n) gp(d.P)[(size_t)t * n * n + i * n + j] = v;
+      if (tid < kS) {
+        double w = spa[tid];
+#pragma unroll 8
+        for (int l = 0; l < kS; ++l) w = fma(sHux[l * kS + tid], skv[l], w);
+        sp[tid] = w;
+        if (tid < n) {
+          if (d.p) gp(d.p)[(size_t)t * n + tid] = w;
+          if (!isfinite(w)) flags[0] = 1;
+        }
+      }
+      // gains and Cholesky factor of this stage, from LDS (coalesced)
+      if (i < m && j < n) gp(d.K)[(size_t)t * m * n + i * n + j] = sK[tid];
+      if (tid < m) gp(d.k)[(size_t)t * m + tid] = skv[tid];
+      if (d.chol && i < m && j < m)
+        gp(d.chol)[(size_t)t * m * m + i * m + j] = j < i ? sLu[i * kS + j] * sD[j] : j == i ? sD[i] : 0.0;
+      if (t > 0) store_stage(smem + (cur ^ 1) * kStageDoubles, next, i, j);
+    }
+    __syncthreads();
+  }
+  const int nonfinite_p = flags[0];
+  __syncthreads();
+  const int nf = rollout(d, 0, T, d.x0, true, smem);
+  if (tid == 0) {
+    const int sweep = (fail == 0 && nonfinite_p) ? LQR_INFO_NONFINITE : fail;
+    *d.info = combine_info(sweep, nf);
+  }
+}
+
+size_t small_serial_lds() {
+  const size_t sweep = kSmallDoubles * sizeof(double) + 64;
+  const size_t roll = rollout_lds(16, 16);
+  return sweep > roll ? sweep : roll;
+}
+
+hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, int ninst,
+                               hipStream_t stream) {
+  const size_t lds = small_serial_lds();
+  hipError_t e = ensure_dynamic_lds((const void*)k_small_serial, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_small_serial, dim3(ninst), dim3(kThreads), lds, stream, single, descs);
+  return hipGetLastError();
+}
+
+}  // namespace lqr

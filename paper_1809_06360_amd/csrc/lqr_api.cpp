@@ -127,6 +127,9 @@ bool is_f32(const lqr_options_t* o) { return o && o->precision == LQR_PREC_FP32;
 // FP32 modes, FP64 matrix cores otherwise.
 int big_engine(const lqr_options_t* o) { return (is_mixed(o) || is_f32(o)) ? 2 : 1; }
 
+// Every instance within the small-size recursion (n, m <= 16; k_small.hip).
+bool small_enough(const BatchPlan& p) { return !p.big && p.max_n <= kSmallMax && p.max_m <= kSmallMax; }
+
 lqr_status_t check_options(const lqr_options_t* o) {
   if (!o) return LQR_SUCCESS;
   if (o->flags & ~(uint32_t)(LQR_FLAG_PHASED | LQR_FLAG_SMOOTHED)) return LQR_ERR_INVALID_ARG;
@@ -594,7 +597,10 @@ lqr_status_t solve_single(const lqr_problem_t* prob, const lqr_options_t* opts, 
         if (e == hipSuccess) e = launch_big_sweep(d, 3, beng, plan.lds3, s);
       }
     } else {
-      if (is_serial(opts)) {
+      if ((is_serial(opts) || d.J == 1) && small_enough(plan)) {
+        // one segment is the plain recursion
+        e = launch_small_serial(d, nullptr, 1, s);
+      } else if (is_serial(opts)) {
         e = launch_serial(d, plan.lds_serial, eng, s);
       } else if (is_smoothed(opts)) {
         e = launch_phase(d, 1, plan.lds1, eng, s);
@@ -717,7 +723,9 @@ lqr_status_t lqr_solve_phase(const lqr_problem_t* prob, const lqr_options_t* opt
         e = launch_big_sweep(d, phase, beng, phase == 1 ? plan.lds1 : plan.lds3, s);
       }
     } else if (is_serial(opts)) {
-      if (phase == 1) e = launch_serial(d, plan.lds_serial, eng, s);
+      if (phase == 1)
+        e = small_enough(plan) ? launch_small_serial(d, nullptr, 1, s)
+                               : launch_serial(d, plan.lds_serial, eng, s);
     } else {
       const size_t lds = phase == 1 ? plan.lds1 : phase == 2 ? plan.lds2 : plan.lds3;
       e = launch_phase(d, phase, lds, eng, s);
@@ -834,7 +842,9 @@ lqr_status_t lqr_solve_batched(const lqr_problem_t* probs, int32_t batch, const 
     // recursion; one workgroup per instance runs it without the task queue.
     bool single = true;
     for (int i = 0; i < batch && single; ++i) single = plan.inst[i].J == 1;
-    if (serial || (single && !is_phased(opts)))
+    if ((serial || (single && !is_phased(opts))) && small_enough(plan))
+      e = launch_small_serial(InstDesc{}, ddesc, batch, s);
+    else if (serial || (single && !is_phased(opts)))
       e = launch_serial_batched(ddesc, batch, plan.max_m, eng, plan.lds_serial, s);
     else if (is_phased(opts))
       e = launch_parallel_batched(ddesc, ditems, plan.nitems, batch, plan.max_n, plan.max_m,

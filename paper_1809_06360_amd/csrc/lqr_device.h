@@ -118,7 +118,7 @@ LQR_DEV Touch touch_stage(const InstDesc& d, int t) {
       if (!p && g < lines) p = base[a] + 16 * g;
       if (!p) g -= lines;
     }
-    h.v[k] = p ? *p : 0.0;
+    h.v[k] = p ? *gp(p) : 0.0;
   }
   return h;
 }
@@ -150,7 +150,7 @@ LQR_DEV void load_stage(const InstDesc& d, int t, const SweepLds& s) {
   const int n = d.n, m = d.m;
   load_block(s.X, s.WX, d.B + (size_t)t * n * m, m, n, m);
   load_block(s.X + m, s.WX, d.A + (size_t)t * n * n, n, n, n);
-  const double* ct = d.c + (size_t)t * n;
+  const LQR_GLOBAL double* ct = gp(d.c + (size_t)t * n);
   for (int i = threadIdx.x; i < n; i += kThreads) s.X[i * s.WX + m + n] = ct[i];
 }
 
@@ -171,9 +171,9 @@ LQR_DEV void stage_products(const InstDesc& d, const SweepLds& s) {
 template <int MM, int E>
 LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncols) {
   const int n = d.n, m = d.m, W = s.W;
-  const double* Rt = d.R + (size_t)t * m * m;
-  const double* St = d.S ? d.S + (size_t)t * m * n : nullptr;
-  const double* rt = d.r + (size_t)t * m;
+  const LQR_GLOBAL double* Rt = gp(d.R + (size_t)t * m * m);
+  const LQR_GLOBAL double* St = d.S ? gp(d.S + (size_t)t * m * n) : nullptr;
+  const LQR_GLOBAL double* rt = gp(d.r + (size_t)t * m);
   double* G = s.G;
   const int mp = s.mp;
   pgemm_sub<E, true, false, false, false>(m, ncols, n, s.X, s.WX, s.Y, W, 0, s.X, s.WX, s.Y, W,
@@ -194,8 +194,10 @@ LQR_DEV void stage_hessian(const InstDesc& d, int t, const SweepLds& s, int ncol
 template <int MM, int E>
 LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg, double* pg) {
   const int n = d.n, m = d.m, W = s.W;
-  const double* Qt = d.Q + (size_t)t * n * n;
-  const double* qt = d.q + (size_t)t * n;
+  const LQR_GLOBAL double* Qt = gp(d.Q + (size_t)t * n * n);
+  const LQR_GLOBAL double* qt = gp(d.q + (size_t)t * n);
+  LQR_GLOBAL double* Pgg = gp(Pg);
+  LQR_GLOBAL double* pgg = gp(pg);
   double* P = s.P;
   double* p = s.p;
   const int ldp = s.ldp;
@@ -206,15 +208,15 @@ LQR_DEV void stage_value(const InstDesc& d, int t, const SweepLds& s, double* Pg
             v += 0.5 * (Qt[i * n + j] + Qt[j * n + i]);
             P[i * ldp + j] = v;
             P[j * ldp + i] = v;
-            if (Pg) {
-              Pg[i * n + j] = v;
-              Pg[j * n + i] = v;
+            if (Pgg) {
+              Pgg[i * n + j] = v;
+              Pgg[j * n + i] = v;
             }
           }
         } else {
           v += qt[i];
           p[i] = v;
-          if (pg) pg[i] = v;
+          if (pgg) pgg[i] = v;
           if (!isfinite(v)) s.bad[1] = 1;  // non-finite value gradient
         }
       },
@@ -259,8 +261,8 @@ LQR_DEV int plain_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
     stage_value<MM, E>(d, t, s, d.P ? d.P + (size_t)t * n * n : nullptr,
                 d.p ? d.p + (size_t)t * n : nullptr);
     {  // [K | k] = -H^{-1}[H_ux | h_u] = -(L^{-1})' Z
-      double* Kt = d.K + (size_t)t * m * n;
-      double* kt = d.k + (size_t)t * m;
+      LQR_GLOBAL double* Kt = gp(d.K + (size_t)t * m * n);
+      LQR_GLOBAL double* kt = gp(d.k + (size_t)t * m);
       const int mp = s.mp;
       pgemm_sub<fp64_engine(E), false, false, false, true>(m, n + 1, 0, s.G, mp, s.G, mp, m, s.G, mp, s.G + m * mp, mp,
           [=](int i, int j, double v) {
@@ -353,8 +355,8 @@ LQR_DEV int dual_sweep(const InstDesc& d, int t0, int t1, double* out, const Swe
   store_block(out + nn, n, Gam, W, n, n);
   store_block(out + 2 * nn, n, s.Psi, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) {
-    out[3 * nn + i] = s.p[i];
-    out[3 * nn + n + i] = s.psi[i];
+    gp(out)[3 * nn + i] = s.p[i];
+    gp(out)[3 * nn + n + i] = s.psi[i];
   }
   return fail;
 }
@@ -394,10 +396,10 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
   int fail = 0;
   for (int t = t1 - 1; t >= t0; --t) {
     const double* At = d.A + (size_t)t * nn;
-    const double* ct = d.c + (size_t)t * n;
-    const double* Rt = d.R + (size_t)t * m * m;
-    const double* St = d.S ? d.S + (size_t)t * m * n : nullptr;
-    const double* rt = d.r + (size_t)t * m;
+    const LQR_GLOBAL double* ct = gp(d.c + (size_t)t * n);
+    const LQR_GLOBAL double* Rt = gp(d.R + (size_t)t * m * m);
+    const LQR_GLOBAL double* St = d.S ? gp(d.S + (size_t)t * m * n) : nullptr;
+    const LQR_GLOBAL double* rt = gp(d.r + (size_t)t * m);
     load_block(X, WX, d.B + (size_t)t * n * m, m, n, m);
     for (int i = threadIdx.x; i < n; i += kThreads) X[i * WX + m] = ct[i];
     __builtin_amdgcn_sched_barrier(0);  // keep the warming loads behind the staging waits
@@ -428,8 +430,8 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     ldl_columns<MM>(G, mp, m, 2 * n + 1, false, nullptr, 0, nullptr, Eb, bad);
     fail = note_pivot(fail, *bad, t);
     {  // [P | p] <- [Q | q] + A'[PA | Pc+p] - Z_ux'[Z_ux | z_h]
-      const double* Qt = d.Q + (size_t)t * nn;
-      const double* qt = d.q + (size_t)t * n;
+      const LQR_GLOBAL double* Qt = gp(d.Q + (size_t)t * nn);
+      const LQR_GLOBAL double* qt = gp(d.q + (size_t)t * n);
       pgemm_sub<E, true, false, false, true>(n, n + 1, n, At, n, Y + m, WY, m, G + m * mp, mp,
           G + m * mp, mp,
           [=](int i, int j, double v) {
@@ -473,8 +475,8 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
   store_block(out, n, P, ldp, n, n);
   if (Gam != out + nn) store_block(out + nn, n, Gam, n, n, n);
   for (int i = threadIdx.x; i < n; i += kThreads) {
-    out[3 * nn + i] = p[i];
-    out[3 * nn + n + i] = psi[i];
+    gp(out)[3 * nn + i] = p[i];
+    gp(out)[3 * nn + n + i] = psi[i];
   }
   __syncthreads();
   return fail;
@@ -485,7 +487,7 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
 LQR_DEV void load_row_block(double (&r)[16], const double* M, int ld, int rows, int cols, int c0, int cw,
                             int lane) {
   const bool ok = lane < rows;
-  const double* row = M + (size_t)(ok ? lane : 0) * ld + c0;
+  const LQR_GLOBAL double* row = gp(M + (size_t)(ok ? lane : 0) * ld + c0);
 #pragma unroll
   for (int q = 0; q < 16; ++q) r[q] = (ok && q < cw && c0 + q < cols) ? row[q] : 0.0;
 }
@@ -527,18 +529,18 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
   // value (P_t, p_t), gain (K_t, k_t) and dynamics (A_t, B_t, c_t) of stage t
   auto fetch_value = [&](int t) {
     load_row_block(pP, d.P + (size_t)t * n * n, n, n, n, n0, cn, lane);
-    bp = rn ? d.p[(size_t)t * n + lane] : 0.0;
+    bp = rn ? gp(d.p)[(size_t)t * n + lane] : 0.0;
   };
   auto fetch_gain = [&](int t) {
     load_row_block(pK, d.K + (size_t)t * m * n, n, m, n, n0, cn, lane);
-    bk = rm ? d.k[(size_t)t * m + lane] : 0.0;
+    bk = rm ? gp(d.k)[(size_t)t * m + lane] : 0.0;
   };
   auto fetch_dyn = [&](int t) {
     load_row_block(pA, d.A + (size_t)t * n * n, n, n, n, n0, cn, lane);
     load_row_block(pB, d.B + (size_t)t * n * m, m, n, m, m0, cm, lane);
-    bc = rn ? d.c[(size_t)t * n + lane] : 0.0;
+    bc = rn ? gp(d.c)[(size_t)t * n + lane] : 0.0;
   };
-  double x = rn ? xs[lane] : 0.0, u = 0.0;
+  double x = rn ? gp(xs)[lane] : 0.0, u = 0.0;
   bool finite = true;  // every value this lane wrote so far
   if (t0 < t1) {
     if (want_lam) fetch_value(t0);
@@ -549,7 +551,7 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
   }
   for (int t = t0; t < t1; ++t) {
     const bool more = t + 1 < t1;
-    if (wave == 0 && rn) d.x[(size_t)t * n + lane] = x;
+    if (wave == 0 && rn) gp(d.x)[(size_t)t * n + lane] = x;
     // partial P x and K x over this wave's columns
     part1[wave * 128 + lane] = want_lam ? row_block_dot(pP, x, n0, cn, 0.0) : 0.0;
     part1[wave * 128 + 64 + lane] = row_block_dot(pK, x, n0, cn, 0.0);
@@ -564,12 +566,12 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
       su += part1[w * 128 + 64 + lane];
     }
     if (want_lam && wave == 2 && rn) {
-      d.lam[(size_t)t * n + lane] = cp + sl;
+      gp(d.lam)[(size_t)t * n + lane] = cp + sl;
       finite = finite && isfinite(cp + sl);
     }
     u = rm ? ck + su : 0.0;
     finite = finite && isfinite(x) && isfinite(u);
-    if (wave == 1 && rm) d.u[(size_t)t * m + lane] = u;
+    if (wave == 1 && rm) gp(d.u)[(size_t)t * m + lane] = u;
     // partial A x + B u
     part2[wave * 64 + lane] = row_block_dot(pB, u, m0, cm, row_block_dot(pA, x, n0, cn, 0.0));
     const double cb = bc;
@@ -581,7 +583,7 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
     x = rn ? cb + sx : 0.0;
   }
   if (last) {
-    if (wave == 0 && rn) d.x[(size_t)T * n + lane] = x;
+    if (wave == 0 && rn) gp(d.x)[(size_t)T * n + lane] = x;
     finite = finite && isfinite(x);
     if (want_lam) {
       part1[wave * 128 + lane] = row_block_dot(pP, x, n0, cn, 0.0);
@@ -590,7 +592,7 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) sl += part1[w * 128 + lane];
       if (wave == 2 && rn) {
-        d.lam[(size_t)T * n + lane] = bp + sl;
+        gp(d.lam)[(size_t)T * n + lane] = bp + sl;
         finite = finite && isfinite(bp + sl);
       }
     }
@@ -613,7 +615,7 @@ LQR_DEV void write_terminal(const InstDesc& d) {
   const int n = d.n, T = d.T;
   if (d.P) store_block(d.P + (size_t)T * n * n, n, d.Q + (size_t)T * n * n, n, n, n);
   if (d.p)
-    for (int i = threadIdx.x; i < n; i += kThreads) d.p[(size_t)T * n + i] = d.q[(size_t)T * n + i];
+    for (int i = threadIdx.x; i < n; i += kThreads) gp(d.p)[(size_t)T * n + i] = gp(d.q)[(size_t)T * n + i];
 }
 
 template <int MM, int E>

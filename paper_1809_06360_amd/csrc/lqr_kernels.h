@@ -26,6 +26,11 @@ hipError_t launch_parallel_batched(const InstDesc* descs, const WorkItem* items,
                                    size_t lds3, int eng, hipStream_t stream);
 hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, int eng, size_t lds,
                                  hipStream_t stream);
+// Plain recursion for instances with n <= 16 and m <= 16 (k_small.hip): the
+// single instance `single` when descs is null, else descs[0 .. ninst).
+hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, int ninst,
+                               hipStream_t stream);
+constexpr int kSmallMax = 16;
 
 // lqr_solve on a caller-given device buffer of ws_bytes (lqr_api.cpp): the
 // workspace of lqr_solve or the scratch array of lqr_solve_noalloc. Launches

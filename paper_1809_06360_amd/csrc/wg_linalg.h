@@ -16,6 +16,17 @@
 
 #define LQR_DEV __device__ __forceinline__
 
+// Global-memory access through a pointer into device memory. Accesses through
+// a generic pointer compile to flat_* instructions, which count in lgkmcnt as
+// well as vmcnt, so every wait for an LDS access would also wait for all
+// global loads and stores in flight; through a global address-space pointer
+// they are global_* instructions, counted in vmcnt only.
+#define LQR_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+LQR_DEV LQR_GLOBAL T* gp(T* p) {
+  return (LQR_GLOBAL T*)p;
+}
+
 namespace lqr {
 
 constexpr int kThreads = 256;
@@ -131,6 +142,7 @@ LQR_DEV void load_block(T* dst, int ldd, const T* __restrict__ src, int lds, int
   const int total = rows * cols;
   const int di = kThreads / cols, dj = kThreads - di * cols;
   int i = threadIdx.x / cols, j = threadIdx.x - i * cols;
+  const LQR_GLOBAL T* gsrc = gp(src);
   for (int e0 = threadIdx.x; e0 < total; e0 += U * kThreads) {
     T v[U];
     int ii[U], jj[U];
@@ -138,7 +150,7 @@ LQR_DEV void load_block(T* dst, int ldd, const T* __restrict__ src, int lds, int
     for (int u = 0; u < U; ++u) {
       ii[u] = i;
       jj[u] = j;
-      v[u] = e0 + u * kThreads < total ? src[i * lds + j] : T(0);
+      v[u] = e0 + u * kThreads < total ? gsrc[i * lds + j] : T(0);
       i += di;
       j += dj;
       if (j >= cols) {
@@ -158,7 +170,7 @@ LQR_DEV void load_block_t(T* dst, int ldd, const T* __restrict__ src, int lds, i
   const int total = rows * cols;
   for (int e = threadIdx.x; e < total; e += kThreads) {
     const int j = e / rows, i = e - j * rows;   // consecutive threads walk a source row
-    dst[i * ldd + j] = src[j * lds + i];
+    dst[i * ldd + j] = gp(src)[j * lds + i];
   }
 }
 
@@ -167,7 +179,7 @@ LQR_DEV void store_block(T* __restrict__ dst, int ldd, const T* src, int lds, in
   const int total = rows * cols;
   for (int e = threadIdx.x; e < total; e += kThreads) {
     const int i = e / cols, j = e - i * cols;
-    dst[i * ldd + j] = src[i * lds + j];
+    gp(dst)[i * ldd + j] = src[i * lds + j];
   }
 }
 
@@ -380,7 +392,7 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
       if (wave == 0 && isH && chol) {
 #pragma unroll
         for (int i = 0; i < MAXM; ++i)
-          if (i < m) chol[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
+          if (i < m) gp(chol)[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
       }
       if (isR) {
         double* dst = fromG ? G + (m + r) * ldg : zi + q * ldzi;
@@ -428,7 +440,7 @@ LQR_DEV void ldl_columns(double* G, int ldg, int m, int nr, bool ident, double* 
       if (chol) {
 #pragma unroll
         for (int i = 0; i < MAXM; ++i)
-          if (i < m) chol[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
+          if (i < m) gp(chol)[i * m + lane] = (i == lane) ? sc : (i > lane ? v[i] / sc : 0.0);
       }
     }
     if (badf && lane == 0) *bad = badf;

@@ -63,8 +63,9 @@ def test_named_workloads_match_oracle(key, algo):
     print(w.name, algo, {k: "%.2e" % v for k, v in errs.items()})
 
 
-def test_single_segment_equals_serial_kernel_bitwise():
-    prob = make_instance(20, 0, 12, 5, 30)
+@pytest.mark.parametrize("n", [12, 20])   # the small-size kernel, the general one
+def test_single_segment_equals_serial_kernel_bitwise(n):
+    prob = make_instance(20, 0, n, 5, 30)
     a = _solve(prob, segments=1, algo="parallel")
     b = _solve(prob, algo="serial")
     for k in ("K", "k", "P", "p", "x", "u", "lam"):
@@ -138,10 +139,14 @@ def test_batched_uneven_matches_oracle_and_single_calls():
         compare(got, oracle.solve(p), label="instance %d %s" % (i, dims[i]))
         if dims[i][3] > 0:
             # single-instance calls link J >= 8 segments by the logarithmic-depth
-            # scan (different rounding); below that both link serially
+            # scan (different rounding); below that both link serially. A
+            # single small instance with one segment runs the small-size
+            # recursion, the batch (n up to 48) the general one.
             single = _solve(p, segments=dims[i][3])
+            n, m, _, J = dims[i]
+            same_kernel = 1 < J < 8 or (J == 1 and max(n, m) > 16)
             for k in ("K", "k", "P", "p", "x", "u"):
-                if dims[i][3] < 8:
+                if same_kernel:
                     assert np.array_equal(got[k], single[k]), (i, k)
                 else:
                     assert rel_err(got[k], single[k]) <= 1e-12, (i, k)

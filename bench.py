@@ -377,7 +377,8 @@ def run_single(args, key, steps, warmup, serial_steps, cpu_seconds, with_mixed_l
         "info": info,
         "phase_ms": {names[p]: v for p, v in kern_ms.items()},
         "serial_gpu": {"solves_per_s": 1e3 / serial_ms, "ms_per_solve": serial_ms,
-                       "kernel": "k_big_serial" if big else "k_serial"},
+                       "kernel": "k_big_serial" if big else
+                                 "k_small_serial" if max(n, m) <= 16 else "k_serial"},
         "speedup_vs_serial_gpu": serial_ms / ms_per_step,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -492,8 +493,9 @@ def run_diff(args, w, cpu_workers):
         "max_rel_err": rel,
         "fp32": {"forward_ms": fwd32, "backward_ms": bwd32, "max_rel_err": rel32,
                  "solves_per_s": w.batch * 1e3 / (fwd32 + bwd32),
-                 "note": "float inputs/outputs staged as double in the workspace; float "
-                         "matrix-core products, double factorizations; adjoint in double"},
+                 "note": "float inputs/outputs staged as double in the workspace; at n, m <= 16 "
+                         "the forward recursion runs in double (the small-size kernel), else "
+                         "float matrix-core products with double factorizations; adjoint in double"},
         "roofline": {"kernel": "lqr_backward (k_adjoint_solve + k_adjoint_grad)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": bwd},

@@ -21,8 +21,8 @@ namespace lqr {
 namespace {
 
 // Solve (L L') y = b in place for one m-vector b in LDS, L row-major (m x m,
-// lower) in global memory; run by wave 0 (lane = row), m sequential steps per
-// triangle with wave-level ordering only.
+// lower) in LDS; run by wave 0 (lane = row), m sequential steps per triangle
+// with wave-level ordering only.
 LQR_DEV void chol_solve_wave(const double* L, int m, double* b) {
   const int lane = threadIdx.x & 63;
   for (int k = 0; k < m; ++k) {  // L z = b
@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
   double* sx = sh2 + m;   // xhat_t (n)
   double* sxn = sx + n;   // xhat_{t+1} (n)
   double* su = sxn + n;   // uhat_t (m)
+  double* sL = su + m;    // Cholesky factor of stage t's input Hessian (m x m)
 
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const double v = -a.dl_dx[(size_t)T * n + i];
@@ -73,12 +74,16 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
   }
   __syncthreads();
   for (int t = T - 1; t >= 0; --t) {
-    const double* At = a.A + (size_t)t * n * n;
-    const double* Bt = a.B + (size_t)t * n * m;
-    const double* Kt = a.K + (size_t)t * m * n;
+    const LQR_GLOBAL double* At = gp(a.A + (size_t)t * n * n);
+    const LQR_GLOBAL double* Bt = gp(a.B + (size_t)t * n * m);
+    const LQR_GLOBAL double* Kt = gp(a.K + (size_t)t * m * n);
+    // the factor to LDS, so that the substitutions' chain of 2m dependent
+    // steps reads no global memory
+    const LQR_GLOBAL double* Lt = gp(a.chol + (size_t)t * m * m);
+    for (int e = threadIdx.x; e < m * m; e += kThreads) sL[e] = Lt[e];
     // hhat = rhat + B' phat  (column i of B against phat)
     for (int i = threadIdx.x; i < m; i += kThreads) {
-      double s = -a.dl_du[(size_t)t * m + i];
+      double s = -gp(a.dl_du)[(size_t)t * m + i];
       for (int l = 0; l < n; ++l) s = fma(Bt[l * m + i], sp[l], s);
       sh[i] = s;
       sh2[i] = s;
@@ -88,17 +93,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
     double acc = 0.0;
     const int i = threadIdx.x;
     if (i < n) {
-      acc = -a.dl_dx[(size_t)t * n + i];
+      acc = -gp(a.dl_dx)[(size_t)t * n + i];
       for (int l = 0; l < n; ++l) acc = fma(At[l * n + i], sp[l], acc);
       for (int l = 0; l < m; ++l) acc = fma(Kt[l * n + i], sh2[l], acc);
     }
-    if (threadIdx.x < 64) chol_solve_wave(a.chol + (size_t)t * m * m, m, sh);
+    if (threadIdx.x < 64) chol_solve_wave(sL, m, sh);
     __syncthreads();
     if (i < n) {
       sp[i] = acc;
-      ph[(size_t)t * n + i] = acc;
+      gp(ph)[(size_t)t * n + i] = acc;
     }
-    for (int j = threadIdx.x; j < m; j += kThreads) kh[(size_t)t * m + j] = -sh[j];
+    for (int j = threadIdx.x; j < m; j += kThreads) gp(kh)[(size_t)t * m + j] = -sh[j];
     __syncthreads();
   }
   // forward: xhat_0 = 0

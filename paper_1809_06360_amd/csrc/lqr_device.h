@@ -502,7 +502,8 @@ LQR_DEV double row_block_dot(const double (&r)[16], double v, int c0, int cw, do
 }
 
 // Forward simulation of stages [t0, t1) from x_{t0} = xs (global):
-// u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t; writes x_t, u_t
+// u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t (c_t = 0 when d.c is
+// null); writes x_t, u_t
 // (and lam_t = P_t x_t + p_t when requested), plus x_T (lam_T) if last.
 // Returns LQR_INFO_NONFINITE (uniformly) if any value it wrote is not finite,
 // else 0. n, m <= 64. Every wave holds the state in registers (lane i: x_i, u_i).
@@ -538,7 +539,7 @@ LQR_DEV int rollout(const InstDesc& d, int t0, int t1, const double* xs, bool la
   auto fetch_dyn = [&](int t) {
     load_row_block(pA, d.A + (size_t)t * n * n, n, n, n, n0, cn, lane);
     load_row_block(pB, d.B + (size_t)t * n * m, m, n, m, m0, cm, lane);
-    bc = rn ? gp(d.c)[(size_t)t * n + lane] : 0.0;
+    bc = (rn && d.c) ? gp(d.c)[(size_t)t * n + lane] : 0.0;
   };
   double x = rn ? gp(xs)[lane] : 0.0, u = 0.0;
   bool finite = true;  // every value this lane wrote so far

@@ -44,7 +44,9 @@ constexpr int kAdjStages = 8;
 LQR_HD size_t adj_ws_doubles(int n, int m, int T) {
   return 3 * (size_t)(T + 1) * n + 2 * (size_t)T * m;
 }
-LQR_HD size_t adj_lds(int n, int m) { return (3 * (size_t)n + 3 * (size_t)m) * 8 + 64; }
+LQR_HD size_t adj_lds(int n, int m) {
+  return (3 * (size_t)n + 3 * (size_t)m + (size_t)m * m) * 8 + 64;
+}
 
 // A unit of batched work: instance index and segment index.
 struct WorkItem {

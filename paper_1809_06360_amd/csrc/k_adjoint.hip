@@ -14,6 +14,7 @@
 // lamhat_t = P_t xhat_t + phat_t. The gradients are outer products of the two
 // solutions (see k_adjoint_grad).
 #include "lqr_device.h"
+#include "lqr_kernels.h"
 #include "lqr_launch.h"
 
 namespace lqr {
@@ -45,7 +46,196 @@ LQR_DEV void chol_solve_wave(const double* L, int m, double* b) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// n, m <= 16: blocks zero-padded to 16 x 16 in a double-buffered LDS area.
+// Thread (i, j) = (tid / 16, tid % 16) loads element (i, j) of the next
+// stage's blocks into registers at the top of a stage and stores them into
+// the other buffer at its end, so no global load sits on the recursion's
+// chain. The substitutions with the Cholesky factor run in registers of
+// wave 0 (lane r holds row r; the pivot value comes by readlane).
+// ---------------------------------------------------------------------------
+constexpr int kAS = 16, kAB = kAS * kAS;
+// one buffer: four blocks and two vectors
+constexpr int kAdjBuf = 4 * kAB + 2 * kAS;
+constexpr int kAdjSmallDoubles = 2 * kAdjBuf + 7 * kAS;
+
+struct AdjRegs {
+  double b0, b1, b2, b3, v;
+};
+
+// Backward stage t: A, B, K, L and (j == 0) qhat_t = -dl/dx_t, (j == 1)
+// rhat_t = -dl/du_t.
+LQR_DEV AdjRegs fetch_back(const AdjDesc& a, int t, int i, int j) {
+  const int n = a.n, m = a.m;
+  AdjRegs g;
+  g.b0 = (i < n && j < n) ? gp(a.A)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.b1 = (i < n && j < m) ? gp(a.B)[(size_t)t * n * m + i * m + j] : 0.0;
+  g.b2 = (i < m && j < n) ? gp(a.K)[(size_t)t * m * n + i * n + j] : 0.0;
+  g.b3 = (i < m && j < m) ? gp(a.chol)[(size_t)t * m * m + i * m + j] : 0.0;
+  g.v = 0.0;
+  if (j == 0 && i < n) g.v = -gp(a.dl_dx)[(size_t)t * n + i];
+  if (j == 1 && i < m) g.v = -gp(a.dl_du)[(size_t)t * m + i];
+  return g;
+}
+
+// Forward stage t: P, K, A, B and (j == 0) khat_t, (j == 1) phat_t.
+LQR_DEV AdjRegs fetch_fwd(const AdjDesc& a, const double* kh, const double* ph, int t, int i, int j) {
+  const int n = a.n, m = a.m, T = a.T;
+  AdjRegs g;
+  g.b0 = (i < n && j < n) ? gp(a.P)[(size_t)t * n * n + i * n + j] : 0.0;
+  const bool st = t < T;  // stage T has only P and phat
+  g.b1 = (st && i < m && j < n) ? gp(a.K)[(size_t)t * m * n + i * n + j] : 0.0;
+  g.b2 = (st && i < n && j < n) ? gp(a.A)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.b3 = (st && i < n && j < m) ? gp(a.B)[(size_t)t * n * m + i * m + j] : 0.0;
+  g.v = 0.0;
+  if (st && j == 0 && i < m) g.v = gp(kh)[(size_t)t * m + i];
+  if (j == 1 && i < n) g.v = gp(ph)[(size_t)t * n + i];
+  return g;
+}
+
+LQR_DEV void store_regs(double* buf, const AdjRegs& g, int i, int j) {
+  const int e = i * kAS + j;
+  buf[e] = g.b0;
+  buf[kAB + e] = g.b1;
+  buf[2 * kAB + e] = g.b2;
+  buf[3 * kAB + e] = g.b3;
+  if (j < 2) buf[4 * kAB + j * kAS + i] = g.v;
+}
+
+LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
+  const int n = a.n, m = a.m, T = a.T;
+  const int tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63;
+  double* ph = a.ws;
+  double* kh = ph + (size_t)(T + 1) * n;
+  double* xh = kh + (size_t)T * m;
+  double* uh = xh + (size_t)(T + 1) * n;
+  double* lh = uh + (size_t)T * m;
+  double* sv = smem + 2 * kAdjBuf;
+  double* sp = sv;            // phat_{t+1}
+  double* sh = sp + kAS;      // hhat_t
+  double* sacc = sh + kAS;    // qhat_t + A_t' phat_{t+1}
+  double* sx0 = sacc + kAS;   // xhat (ping-pong with sx1)
+  double* sx1 = sx0 + kAS;
+  double* su = sx1 + kAS;     // uhat_t
+  double* srd = su + kAS;     // 1 / L_t(k, k)
+
+  // backward
+  if (tid < kAS) {
+    const double v = tid < n ? -gp(a.dl_dx)[(size_t)T * n + tid] : 0.0;
+    sp[tid] = v;
+    if (tid < n) gp(ph)[(size_t)T * n + tid] = v;
+  }
+  store_regs(smem, fetch_back(a, T - 1, i, j), i, j);
+  __syncthreads();
+  for (int t = T - 1, cur = 0; t >= 0; --t, cur ^= 1) {
+    const double* bA = smem + cur * kAdjBuf;
+    const double* bB = bA + kAB;
+    const double* bK = bA + 2 * kAB;
+    const double* bL = bA + 3 * kAB;
+    const double* bq = bA + 4 * kAB;
+    const double* br = bq + kAS;
+    const AdjRegs next = fetch_back(a, t > 0 ? t - 1 : 0, i, j);
+    // hhat = rhat + B' phat (wave 0), qhat + A' phat (wave 1)
+    double hv = 0.0;
+    if (tid < 64) {
+      const int r = lane & 15;
+      hv = br[r];
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) hv = fma(bB[l * kAS + r], sp[l], hv);
+      if (lane < kAS) sh[lane] = hv;
+    } else if (tid < 128) {
+      const int r = lane & 15;
+      double v = bq[r];
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) v = fma(bA[l * kAS + r], sp[l], v);
+      if (lane < kAS) sacc[lane] = v;
+    } else if (tid < 128 + kAS) {
+      const int r = tid - 128;  // reciprocals of the factor's diagonal, off the chain
+      srd[r] = r < m ? 1.0 / bL[r * kAS + r] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // (L L') y = hhat: lane r holds y_r; rows >= m are zero
+      const int r = lane & 15;
+      double y = hv;
+      static_for<0, kAS>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        if (k < m) {
+          const double zk = readlane(y, k) * srd[k];
+          y = r == k ? zk : (r > k ? fma(-bL[r * kAS + k], zk, y) : y);
+        }
+      });
+      static_for<0, kAS>([&](auto Kc) {
+        constexpr int k = kAS - 1 - decltype(Kc)::value;
+        if (k < m) {
+          const double yk = readlane(y, k) * srd[k];
+          y = r == k ? yk : (r < k ? fma(-bL[k * kAS + r], yk, y) : y);
+        }
+      });
+      if (lane < m) gp(kh)[(size_t)t * m + lane] = -y;
+    } else if (tid < 128) {
+      // phat_t = qhat + A' phat + K' hhat
+      const int r = lane & 15;
+      double v = sacc[r];
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) v = fma(bK[l * kAS + r], sh[l], v);
+      if (lane < kAS) sp[lane] = v;
+      if (lane < n) gp(ph)[(size_t)t * n + lane] = v;
+    }
+    if (t > 0) store_regs(smem + (cur ^ 1) * kAdjBuf, next, i, j);
+    __syncthreads();
+  }
+  // forward from xhat_0 = 0
+  if (tid < kAS) sx0[tid] = 0.0;
+  store_regs(smem, fetch_fwd(a, kh, ph, 0, i, j), i, j);
+  __syncthreads();
+  for (int t = 0, cur = 0; t <= T; ++t, cur ^= 1) {
+    const double* bP = smem + cur * kAdjBuf;
+    const double* bK = bP + kAB;
+    const double* bA = bP + 2 * kAB;
+    const double* bB = bP + 3 * kAB;
+    const double* bk = bP + 4 * kAB;
+    const double* bp = bk + kAS;
+    double* sx = (t & 1) ? sx1 : sx0;
+    double* sxn = (t & 1) ? sx0 : sx1;
+    const AdjRegs next = fetch_fwd(a, kh, ph, t < T ? t + 1 : T, i, j);
+    // uhat = K xhat + khat (wave 0), lamhat = P xhat + phat (wave 1), xhat out (wave 2)
+    if (tid < 64) {
+      const int r = lane & 15;
+      double u = bk[r];
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) u = fma(bK[r * kAS + l], sx[l], u);
+      if (t < T && lane < kAS) su[lane] = u;
+      if (t < T && lane < m) gp(uh)[(size_t)t * m + lane] = u;
+    } else if (tid < 128) {
+      const int r = lane & 15;
+      double v = bp[r];
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) v = fma(bP[r * kAS + l], sx[l], v);
+      if (lane < n) gp(lh)[(size_t)t * n + lane] = v;
+    } else if (tid < 192) {
+      if (lane < n) gp(xh)[(size_t)t * n + lane] = sx[lane];
+    }
+    if (t == T) break;
+    __syncthreads();
+    // xhat_{t+1} = A xhat + B uhat (wave 0)
+    if (tid < 64) {
+      const int r = lane & 15;
+      double v = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) v = fma(bA[r * kAS + l], sx[l], v);
+#pragma unroll 8
+      for (int l = 0; l < kAS; ++l) v = fma(bB[r * kAS + l], su[l], v);
+      if (lane < kAS) sxn[lane] = v;
+    }
+    store_regs(smem + (cur ^ 1) * kAdjBuf, next, i, j);
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+size_t adjoint_small_lds() { return (size_t)kAdjSmallDoubles * sizeof(double) + 64; }
 
 // One workgroup per instance: the adjoint backward and forward recursions.
 // Workspace per instance (AdjDesc::ws): phat (T+1)n | khat T m | xhat (T+1)n |
@@ -54,6 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
   extern __shared__ double smem[];
   const AdjDesc a = descs[blockIdx.x];
   const int n = a.n, m = a.m, T = a.T;
+  if (n <= kAS && m <= kAS) {
+    adjoint_small(a, smem);
+    return;
+  }
   double* ph = a.ws;
   double* kh = ph + (size_t)(T + 1) * n;
   double* xh = kh + (size_t)T * m;

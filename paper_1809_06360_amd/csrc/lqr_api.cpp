@@ -364,6 +364,8 @@ lqr_status_t make_adj_plan(const lqr_problem_t* probs, int batch, AdjPlan* ap, b
     if (probs[i].m > 64) return LQR_ERR_UNSUPPORTED;
     nb += adj_blocks(probs[i].T);
     ap->lds = std::max(ap->lds, adj_lds(probs[i].n, probs[i].m));
+    if (probs[i].n <= kSmallMax && probs[i].m <= kSmallMax)
+      ap->lds = std::max(ap->lds, adjoint_small_lds());
   }
   ap->nblocks = nb;
   ap->reg = regions_of(probs, batch);

@@ -31,6 +31,8 @@ hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, in
 hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, int ninst,
                                hipStream_t stream);
 constexpr int kSmallMax = 16;
+// Dynamic LDS of the adjoint solve for an instance with n, m <= 16 (k_adjoint.hip).
+size_t adjoint_small_lds();
 
 // lqr_solve on a caller-given device buffer of ws_bytes (lqr_api.cpp): the
 // workspace of lqr_solve or the scratch array of lqr_solve_noalloc. Launches

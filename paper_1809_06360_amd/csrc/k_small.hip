@@ -32,8 +32,8 @@ constexpr int kB = kS * kS;       // padded block size
 // one half of the stage-input double buffer: A | B | S | Q | R | c | q | r
 constexpr int kStageDoubles = 5 * kB + 3 * kS;
 // LDS carve (doubles): 2 stage buffers, then P | p | Y | W | g | H | Hux | h |
-// K | kv | Lu | Pa | pa | D | zero | Col[2], then an int flag
-constexpr int kSmallDoubles = 2 * kStageDoubles + 8 * kB + 11 * kS;
+// K | kv | Lu | Pa | pa | D | zero, then an int flag
+constexpr int kSmallDoubles = 2 * kStageDoubles + 8 * kB + 9 * kS;
 
 struct StageRegs {
   double a, b, s, q2, r2, v;  // this thread's element of A, B, S, Q, R; of c, q or r
@@ -65,6 +65,47 @@ LQR_DEV void store_stage(double* buf, const StageRegs& g, int i, int j) {
   if (j < 3) buf[5 * kB + j * kS + i] = g.v;
 }
 
+// Rounds of the L_unit D L_unit' elimination and the back substitution for a
+// fixed m = M (wave 0; lane c holds column c of [H | Hux | h]): the pivot and
+// the entries H(r, k), r > k, come from lane k by readlane, so the chain
+// touches no LDS; the multipliers go to Lu for the back substitution and the
+// pivots to D. bad: as note_pivot expects.
+template <int M>
+LQR_DEV void ldl_rounds(double (&v)[kS], int c, int& bad, double* sLu, double* sD) {
+  static_for<0, M>([&](auto Kc) {
+    constexpr int k = decltype(Kc)::value;
+    double dk = readlane(v[k], k);
+    if (!(dk > 0.0) || !isfinite(dk)) {
+      if (!bad) bad = isfinite(dk) ? 1 : 2;
+      dk = __builtin_nan("");
+    }
+    const double tk = v[k] * recip(dk);
+    if (c > k && c < M) sLu[c * kS + k] = tk;
+    if (c == 0) sD[k] = dk;
+    static_for<k + 1, M>([&](auto I) {
+      constexpr int r = decltype(I)::value;
+      v[r] = fma(-readlane(v[r], k), tk, v[r]);
+    });
+    v[k] = tk;
+  });
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  static_for<1, M>([&](auto Ic) {
+    constexpr int r = M - decltype(Ic)::value;  // M-1 .. 1
+    const double xr = v[r];
+    static_for<0, r>([&](auto Kc) {
+      constexpr int k = decltype(Kc)::value;
+      v[k] = fma(-sLu[r * kS + k], xr, v[k]);
+    });
+  });
+}
+
+template <int... Ms>
+LQR_DEV void ldl_dispatch(int m, double (&v)[kS], int c, int& bad, double* sLu, double* sD) {
+  ((m == Ms ? (ldl_rounds<Ms>(v, c, bad, sLu, sD), 0) : 0), ...);
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs) {
@@ -87,8 +128,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
   double* spa = sPa + kB;     // q + A'g
   double* sD = spa + kS;      // pivots of H, then their square roots
   double* sZero = sD + kS;    // 16 zeros
-  double* sCol = sZero + kS;  // [2][16]: the pivot column published in a round
-  int* flags = reinterpret_cast<int*>(sCol + 2 * kS);  // [0]: non-finite value gradient
+  int* flags = reinterpret_cast<int*>(sZero + kS);  // [0]: non-finite value gradient
   const int mx = i > j ? i : j, mn = i > j ? j : i;
 
   write_terminal(d);
@@ -150,9 +190,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
 
     // 3. Wave 0: lane c < m holds column c of H, lane m + c (c < n) column c
     //    of Hux, lane m + n the vector h, other lanes zeros; rows >= m are
-    //    zero and stay zero. Round k: lane k publishes its column in LDS
-    //    (pivot d_k = H(k, k) and H(r, k), r > k), and every lane updates its
-    //    column, v_r -= H(r, k) (v_k / d_k) for r > k. The trailing block stays
+    //    zero and stay zero. Round k reads the pivot d_k = H(k, k) and
+    //    H(r, k), r > k, from lane k (readlane; the rounds are unrolled for the
+    //    instance's m), and every lane updates its column,
+    //    v_r -= H(r, k) (v_k / d_k) for r > k. The trailing block stays
     //    symmetric, so lane c > k's v_k / d_k is the unit lower factor's entry
     //    (c, k), kept in Lu, and v_k / d_k is also the right-hand side's entry
     //    of D^{-1} L_unit^{-1} [Hux | h]. Back substitution with L_unit' then
@@ -167,45 +208,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
       double v[kS];
       static_for<0, kS>([&](auto R) { v[decltype(R)::value] = col[decltype(R)::value * cs]; });
       int bad = 0;
-      static_for<0, kS>([&](auto Kc) {
-        constexpr int k = decltype(Kc)::value;
-        if (k < m) {
-          double* pub = sCol + (k & 1) * kS;  // alternate halves across rounds
-          if (c == k) {
-            static_for<k, kS>([&](auto R) { pub[decltype(R)::value] = v[decltype(R)::value]; });
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          double dk = pub[k];
-          if (!(dk > 0.0) || !isfinite(dk)) {
-            if (!bad) bad = isfinite(dk) ? 1 : 2;
-            dk = __builtin_nan("");
-          }
-          const double tk = v[k] * recip(dk);
-          if (c > k && c < m) sLu[c * kS + k] = tk;
-          if (c == 0) sD[k] = dk;
-          static_for<k + 1, kS>([&](auto I) {
-            constexpr int r = decltype(I)::value;
-            v[r] = fma(-pub[r], tk, v[r]);
-          });
-          v[k] = tk;
-        }
-      });
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // L_unit' x = y from the last row up
-      static_for<1, kS>([&](auto Ic) {
-        constexpr int r = kS - decltype(Ic)::value;  // kS-1 .. 1
-        if (r < m) {
-          const double xr = v[r];
-          static_for<0, r>([&](auto Kc) {
-            constexpr int k = decltype(Kc)::value;
-            v[k] = fma(-sLu[r * kS + k], xr, v[k]);
-          });
-        }
-      });
+      ldl_dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>(m, v, c, bad, sLu, sD);
       if (rcol) {
         static_for<0, kS>([&](auto Kc) { sK[decltype(Kc)::value * kS + (c - m)] = -v[decltype(Kc)::value]; });
       } else if (vcol) {

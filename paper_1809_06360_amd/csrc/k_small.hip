@@ -9,8 +9,8 @@
 // into registers at the top of a stage and stored to the other half of a
 // double buffer at its end, so their latency overlaps the stage's work. A
 // stage costs four barriers:
-//   1. Y = P A, W = P B, g = P c + p                      (all threads)
-//   2. H = R + B'W, Hux = S + B'Y, h = r + B'g            (all threads)
+//   1. Y = P A, W = P B (matrix cores), g = P c + p        (waves 0-2)
+//   2. H = R + B'W, Hux = S + B'Y (matrix cores), h = r + B'g (waves 0-2)
 //   3. H = L_unit D L_unit', [K | k] = -H^{-1}[Hux | h]   (wave 0, see below)
 //      and meanwhile Q + A'Y, q + A'g                     (waves 1-3)
 //   4. P <- (Q + A'Y) + Hux'K, p <- (q + A'g) + Hux'k     (all threads)
@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
 
   write_terminal(d);
   // value at T, the last stage's inputs, zero gains (rows >= m stay zero)
-  sP[tid] = (i < n && j < n) ? gp(d.Q)[(size_t)T * n * n + i * n + j] : 0.0;
+  sP[tid] = (i < n && j < n)
+                ? 0.5 * (gp(d.Q)[(size_t)T * n * n + i * n + j] + gp(d.Q)[(size_t)T * n * n + j * n + i])
+                : 0.0;
   if (tid < kS) sp[tid] = tid < n ? gp(d.q)[(size_t)T * n + tid] : 0.0;
   sK[tid] = 0.0;
   if (tid < kS) {
@@ -156,35 +158,56 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
     const double* br = bq + kS;
     const StageRegs next = fetch_stage(d, t > 0 ? t - 1 : 0, i, j);
 
-    // 1. Y = P A, W = P B, g = P c + p
+    // 1. Y = P A (wave 0) and W = P B (wave 1) on the matrix cores, g = P c + p
+    //    (wave 2). P is exactly symmetric, so its column k is read as row k.
     {
-      double y = 0.0, w = 0.0, gc = 0.0;
+      const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      if (wv < 2) {
+        const double* Yop = wv == 0 ? bA : bB;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + lk;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sP[k * kS + li], Yop[k * kS + li], acc, 0, 0, 0);
+        }
+        double* out = wv == 0 ? sY : sW;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(lk + 4 * r) * kS + li] = acc[r];
+      } else if (wv == 2 && lane < kS) {
+        double gc = sp[lane];
 #pragma unroll 8
-      for (int l = 0; l < kS; ++l) {
-        const double pil = sP[i * kS + l];
-        y = fma(pil, bA[l * kS + j], y);
-        w = fma(pil, bB[l * kS + j], w);
-        gc = fma(pil, bc[l], gc);
+        for (int l = 0; l < kS; ++l) gc = fma(sP[l * kS + lane], bc[l], gc);
+        sg[lane] = gc;
       }
-      sY[tid] = y;
-      sW[tid] = w;
-      if (j == 0) sg[i] = gc + sp[i];
     }
     __syncthreads();
 
-    // 2. H = R + B'W (symmetrised R), Hux = S + B'Y, h = r + B'g
+    // 2. H = R + B'W (symmetrised R; wave 0) and Hux = S + B'Y (wave 1) on the
+    //    matrix cores, h = r + B'g (wave 2)
     {
-      double hh = 0.5 * (bR[i * kS + j] + bR[j * kS + i]), hx = bS[tid], hv = 0.0;
+      const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      if (wv < 2) {
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = lk + 4 * r;
+          acc[r] = wv == 0 ? 0.5 * (bR[ii * kS + li] + bR[li * kS + ii]) : bS[ii * kS + li];
+        }
+        const double* Yop = wv == 0 ? sW : sY;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + lk;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bB[k * kS + li], Yop[k * kS + li], acc, 0, 0, 0);
+        }
+        double* out = wv == 0 ? sH : sHux;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(lk + 4 * r) * kS + li] = acc[r];
+      } else if (wv == 2 && lane < kS) {
+        double hv = br[lane];
 #pragma unroll 8
-      for (int l = 0; l < kS; ++l) {
-        const double bli = bB[l * kS + i];
-        hh = fma(bli, sW[l * kS + j], hh);
-        hx = fma(bli, sY[l * kS + j], hx);
-        hv = fma(bli, sg[l], hv);
+        for (int l = 0; l < kS; ++l) hv = fma(bB[l * kS + lane], sg[l], hv);
+        sh[lane] = hv;
       }
-      sH[tid] = hh;
-      sHux[tid] = hx;
-      if (j == 0) sh[i] = br[i] + hv;
     }
     __syncthreads();
 

@@ -30,12 +30,12 @@ def _outputs(n, m, T, dev):
                 lam=e(T + 1, n), info=torch.full((1,), 12345, dtype=torch.int32, device=dev))
 
 
-def _run_pair(prob_np, J, algo):
+def _run_pair(prob_np, J, algo, smoothed=False):
     import paper_1809_06360_amd as L
     dev = torch.device("cuda:0")
     data = to_device(prob_np)
     T, n, m = prob_np["B"].shape
-    opts = L.options("fp64", algo)
+    opts = L.options("fp64", algo, smoothed=smoothed)
     stream = torch.cuda.current_stream(dev).cuda_stream
     a = _outputs(n, m, T, dev)
     pa = L._problem(data, a, J)
@@ -74,3 +74,21 @@ def test_noalloc_refuses_problems_larger_than_its_scratch():
         L.lqr_solve_noalloc(prob, opts, 0)
     assert e.value.status == L.ERR_WORKSPACE
     assert np.isfinite(need)
+
+
+def test_noalloc_smoothed_policies_match_lqr_solve():
+    """The smoothed-policy option through the no-allocation entry point: two
+    calls in a row, bitwise equal to lqr_solve, gains equal to the oracle's
+    smoothed family."""
+    from oracle import policies as PO
+    big = make_instance(151, 0, 48, 24, 192)       # J = 12: logarithmic-depth linking
+    small = make_instance(151, 1, 12, 6, 96)       # J = 6: serial linking
+    for prob, J in ((big, 12), (small, 6)):
+        a, b = _run_pair(prob, J, "parallel", smoothed=True)
+        assert int(a["info"][0]) == 0 and int(b["info"][0]) == 0
+        for k in OUTS:
+            assert torch.equal(a[k], b[k]), ("smoothed", prob["B"].shape, k)
+        Ks, ks = PO.smoothed_policies(prob, J, oracle.solve(prob))
+        got = {k: a[k].cpu().numpy() for k in ("K", "k")}
+        compare(got, {"K": Ks, "k": ks}, keys=("K", "k"), tol=FP64_TOL,
+                label="noalloc smoothed %s" % (prob["B"].shape,))

@@ -108,10 +108,14 @@ LQR_DEV void ldl_dispatch(int m, double (&v)[kS], int c, int& bad, double* sLu, 
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs) {
-  extern __shared__ double smem[];
-  const InstDesc d = descs ? descs[blockIdx.x] : single;
-  const int n = d.n, m = d.m, T = d.T;
+// Plain recursion over stages [t0, t1) from the value (Pend, pend) at t1
+// (global memory, symmetrised on load); writes K, k, P, p, chol for those
+// stages. Returns a status code as note_pivot builds it (LQR_INFO_NONFINITE
+// also for a non-finite value gradient), uniform over the workgroup. Ends
+// with a barrier; smem may be reused afterwards.
+LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, const double* pend,
+                        double* smem) {
+  const int n = d.n, m = d.m;
   const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
   double* sP = smem + 2 * kStageDoubles;
   double* sp = sP + kB;
@@ -131,23 +135,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
   int* flags = reinterpret_cast<int*>(sZero + kS);  // [0]: non-finite value gradient
   const int mx = i > j ? i : j, mn = i > j ? j : i;
 
-  write_terminal(d);
-  // value at T, the last stage's inputs, zero gains (rows >= m stay zero)
-  sP[tid] = (i < n && j < n)
-                ? 0.5 * (gp(d.Q)[(size_t)T * n * n + i * n + j] + gp(d.Q)[(size_t)T * n * n + j * n + i])
-                : 0.0;
-  if (tid < kS) sp[tid] = tid < n ? gp(d.q)[(size_t)T * n + tid] : 0.0;
+  // value at t1, the last stage's inputs, zero gains (rows >= m stay zero)
+  sP[tid] = (i < n && j < n) ? 0.5 * (gp(Pend)[i * n + j] + gp(Pend)[j * n + i]) : 0.0;
+  if (tid < kS) sp[tid] = tid < n ? gp(pend)[tid] : 0.0;
   sK[tid] = 0.0;
   if (tid < kS) {
     skv[tid] = 0.0;
     sZero[tid] = 0.0;
   }
   if (tid == 0) flags[0] = 0;
-  store_stage(smem, fetch_stage(d, T - 1, i, j), i, j);
+  store_stage(smem, fetch_stage(d, t1 - 1, i, j), i, j);
   __syncthreads();
 
   int fail = 0;  // wave 0's status (note_pivot)
-  for (int t = T - 1, cur = 0; t >= 0; --t, cur ^= 1) {
+  for (int t = t1 - 1, cur = 0; t >= t0; --t, cur ^= 1) {
     const double* bA = smem + cur * kStageDoubles;
     const double* bB = bA + kB;
     const double* bS = bA + 2 * kB;
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
     const double* bc = bA + 5 * kB;
     const double* bq = bc + kS;
     const double* br = bq + kS;
-    const StageRegs next = fetch_stage(d, t > 0 ? t - 1 : 0, i, j);
+    const StageRegs next = fetch_stage(d, t > t0 ? t - 1 : t0, i, j);
 
     // 1. Y = P A (wave 0) and W = P B (wave 1) on the matrix cores, g = P c + p
     //    (wave 2). P is exactly symmetric, so its column k is read as row k.
@@ -282,23 +283,58 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
       if (tid < m) gp(d.k)[(size_t)t * m + tid] = skv[tid];
       if (d.chol && i < m && j < m)
         gp(d.chol)[(size_t)t * m * m + i * m + j] = j < i ? sLu[i * kS + j] * sD[j] : j == i ? sD[i] : 0.0;
-      if (t > 0) store_stage(smem + (cur ^ 1) * kStageDoubles, next, i, j);
+      if (t > t0) store_stage(smem + (cur ^ 1) * kStageDoubles, next, i, j);
     }
     __syncthreads();
   }
   const int nonfinite_p = flags[0];
+  // wave 0's status to every thread
+  if (tid == 0) flags[1] = (fail == 0 && nonfinite_p) ? LQR_INFO_NONFINITE : fail;
   __syncthreads();
+  const int code = flags[1];
+  __syncthreads();
+  return code;
+}
+
+__global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs) {
+  extern __shared__ double smem[];
+  const InstDesc d = descs ? descs[blockIdx.x] : single;
+  const int n = d.n, T = d.T;
+  write_terminal(d);
+  const int sweep = small_sweep(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, smem);
   const int nf = rollout(d, 0, T, d.x0, true, smem);
-  if (tid == 0) {
-    const int sweep = (fail == 0 && nonfinite_p) ? LQR_INFO_NONFINITE : fail;
-    *d.info = combine_info(sweep, nf);
+  if (threadIdx.x == 0) *d.info = combine_info(sweep, nf);
+}
+
+// Phase 3 of the segmented solve at these sizes, one workgroup per segment:
+// the rebuild of segment j < J - 1 from the exact value at its end (the
+// linking solve's boundary slot), then the forward simulation from its
+// boundary state (the last segment was swept in phase 1).
+__global__ __launch_bounds__(kThreads, 2) void k_small_phase3(InstDesc d) {
+  extern __shared__ double smem[];
+  const int n = d.n, T = d.T, J = d.J, seg = blockIdx.x;
+  const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
+  if (seg < J - 1) {
+    const double* b = ws_bnd(d.ws, n, J, seg + 1);
+    const int fail = small_sweep(d, t0, t1, b, b + n * n, smem);
+    if (fail && threadIdx.x == 0) report_info(d.info, fail);
   }
+  const int nf = rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
+  if (nf && threadIdx.x == 0) report_info(d.info, nf);
 }
 
 size_t small_serial_lds() {
   const size_t sweep = kSmallDoubles * sizeof(double) + 64;
   const size_t roll = rollout_lds(16, 16);
   return sweep > roll ? sweep : roll;
+}
+
+hipError_t launch_small_phase3(const InstDesc& d, hipStream_t stream) {
+  const size_t lds = small_serial_lds();
+  hipError_t e = ensure_dynamic_lds((const void*)k_small_phase3, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_small_phase3, dim3(d.J), dim3(kThreads), lds, stream, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, int ninst,

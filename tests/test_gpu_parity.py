@@ -140,11 +140,12 @@ def test_batched_uneven_matches_oracle_and_single_calls():
         if dims[i][3] > 0:
             # single-instance calls link J >= 8 segments by the logarithmic-depth
             # scan (different rounding); below that both link serially. A
-            # single small instance with one segment runs the small-size
-            # recursion, the batch (n up to 48) the general one.
+            # single instance with n, m <= 16 runs its recursion (one segment)
+            # or its rebuild (several) on the small-size kernels, the batch
+            # (n up to 48) on the general ones.
             single = _solve(p, segments=dims[i][3])
             n, m, _, J = dims[i]
-            same_kernel = 1 < J < 8 or (J == 1 and max(n, m) > 16)
+            same_kernel = J < 8 and max(n, m) > 16
             for k in ("K", "k", "P", "p", "x", "u"):
                 if same_kernel:
                     assert np.array_equal(got[k], single[k]), (i, k)

@@ -244,7 +244,8 @@ def run_single(args, key, steps, warmup, serial_steps, cpu_seconds, with_mixed_l
     kern_ms = {ph: float(np.mean([ev[s][ph - 1].elapsed_time(ev[s][ph]) for s in range(steps)]))
                for ph in (1, 2, 3)}
     names = ({1: "k_big_phase1", 2: "linking sequence", 3: "k_big_phase3"} if big else
-             {1: "k_phase1", 2: "linking sequence" if uses_scan(n, J) else "k_phase2",
+             {1: "k_small_phase1" if max(n, m) <= 16 else "k_phase1",
+              2: "linking sequence" if uses_scan(n, J) else "k_phase2",
               3: "k_small_phase3" if max(n, m) <= 16 else "k_phase3"})
     log("timed %d steps: %.3f ms/step; phases %s" % (steps, ms_per_step,
                                                      {names[p]: round(v, 4) for p, v in kern_ms.items()}))

@@ -80,7 +80,10 @@ typedef enum {
                             results widened to double; the input Hessian R + B'PB is
                             assembled and Cholesky-factored in double, the gains and
                             the linking solve are double. lqr_backward computes in
-                            double. */
+                            double. Instances with n <= 16 and m <= 16 run the
+                            small-size kernels, which compute everything in double
+                            whatever the precision (at that size float products save
+                            no time). */
     LQR_PREC_FP32 = 2    /* float inputs and outputs (every array of lqr_problem_t
                             and lqr_grad_t). The call converts them to a double
                             staging area in the workspace, solves as LQR_PREC_MIXED

@@ -32,8 +32,9 @@ constexpr int kB = kS * kS;       // padded block size
 // one half of the stage-input double buffer: A | B | S | Q | R | c | q | r
 constexpr int kStageDoubles = 5 * kB + 3 * kS;
 // LDS carve (doubles): 2 stage buffers, then P | p | Y | W | g | H | Hux | h |
-// K | kv | Lu | Pa | pa | D | zero, then an int flag
-constexpr int kSmallDoubles = 2 * kStageDoubles + 8 * kB + 9 * kS;
+// K | kv | Lu | Pa | pa | D | zero, then (dual form) Gam | W | X | A'Gam |
+// Psi[2] | psi | Gam'c, then two int flags
+constexpr int kSmallDoubles = 2 * kStageDoubles + 14 * kB + 11 * kS;
 
 struct StageRegs {
   double a, b, s, q2, r2, v;  // this thread's element of A, B, S, Q, R; of c, q or r
@@ -110,11 +111,18 @@ LQR_DEV void ldl_dispatch(int m, double (&v)[kS], int c, int& bad, double* sLu, 
 
 // Plain recursion over stages [t0, t1) from the value (Pend, pend) at t1
 // (global memory, symmetrised on load); writes K, k, P, p, chol for those
-// stages. Returns a status code as note_pivot builds it (LQR_INFO_NONFINITE
-// also for a non-finite value gradient), uniform over the workgroup. Ends
-// with a barrier; smem may be reused afterwards.
+// stages. With DUAL, the parametric (dual-form) sweep of a segment instead:
+// the value starts at zero with Gam = I, Psi = 0, psi = 0 at t1, and per stage,
+// with W = B'Gam (the old Gam) and X = H^{-1} W from the same elimination as
+// the gains,
+//   Psi += W'X,  psi += Gam'c + W'k,  Gam <- A'Gam + K'W,
+// no per-stage output is written, and P0 | Gam | Psi | pbar | psi go to `out`
+// at the end. Returns a status code as note_pivot builds it
+// (LQR_INFO_NONFINITE also for a non-finite value gradient), uniform over
+// the workgroup. Ends with a barrier; smem may be reused afterwards.
+template <bool DUAL>
 LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, const double* pend,
-                        double* smem) {
+                        double* out, double* smem) {
   const int n = d.n, m = d.m;
   const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
   double* sP = smem + 2 * kStageDoubles;
@@ -132,12 +140,27 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
   double* spa = sPa + kB;     // q + A'g
   double* sD = spa + kS;      // pivots of H, then their square roots
   double* sZero = sD + kS;    // 16 zeros
-  int* flags = reinterpret_cast<int*>(sZero + kS);  // [0]: non-finite value gradient
+  double* sGam = sZero + kS;  // Gam (dual form)
+  double* sWg = sGam + kB;    // W = B'Gam
+  double* sXg = sWg + kB;     // X = H^{-1} W
+  double* sAG = sXg + kB;     // A'Gam
+  double* sPsi = sAG + kB;    // [2]: Psi, ping-pong across stages
+  double* spsi = sPsi + 2 * kB;
+  double* sGc = spsi + kS;    // Gam'c
+  int* flags = reinterpret_cast<int*>(DUAL ? sGc + kS : sZero + kS);  // [0]: non-finite value gradient
   const int mx = i > j ? i : j, mn = i > j ? j : i;
 
   // value at t1, the last stage's inputs, zero gains (rows >= m stay zero)
-  sP[tid] = (i < n && j < n) ? 0.5 * (gp(Pend)[i * n + j] + gp(Pend)[j * n + i]) : 0.0;
-  if (tid < kS) sp[tid] = tid < n ? gp(pend)[tid] : 0.0;
+  if (DUAL) {
+    sP[tid] = 0.0;
+    if (tid < kS) sp[tid] = 0.0;
+    sGam[tid] = (i == j && i < n) ? 1.0 : 0.0;
+    sPsi[tid] = 0.0;
+    if (tid < kS) spsi[tid] = 0.0;
+  } else {
+    sP[tid] = (i < n && j < n) ? 0.5 * (gp(Pend)[i * n + j] + gp(Pend)[j * n + i]) : 0.0;
+    if (tid < kS) sp[tid] = tid < n ? gp(pend)[tid] : 0.0;
+  }
   sK[tid] = 0.0;
   if (tid < kS) {
     skv[tid] = 0.0;
@@ -149,6 +172,8 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
 
   int fail = 0;  // wave 0's status (note_pivot)
   for (int t = t1 - 1, cur = 0; t >= t0; --t, cur ^= 1) {
+    const double* sPsiOld = sPsi + cur * kB;  // DUAL: this stage's Psi in, the other half out
+    double* sPsiNew = sPsi + (cur ^ 1) * kB;
     const double* bA = smem + cur * kStageDoubles;
     const double* bB = bA + kB;
     const double* bS = bA + 2 * kB;
@@ -179,6 +204,11 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
 #pragma unroll 8
         for (int l = 0; l < kS; ++l) gc = fma(sP[l * kS + lane], bc[l], gc);
         sg[lane] = gc;
+      } else if (DUAL && wv == 3 && lane < kS) {
+        double gc = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < kS; ++l) gc = fma(sGam[l * kS + lane], bc[l], gc);
+        sGc[lane] = gc;
       }
     }
     __syncthreads();
@@ -203,7 +233,16 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
         double* out = wv == 0 ? sH : sHux;
 #pragma unroll
         for (int r = 0; r < 4; ++r) out[(lk + 4 * r) * kS + li] = acc[r];
-      } else if (wv == 2 && lane < kS) {
+      } else if (DUAL && wv == 2) {
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + lk;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bB[k * kS + li], sGam[k * kS + li], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sWg[(lk + 4 * r) * kS + li] = acc[r];
+      } else if (wv == (DUAL ? 3 : 2) && lane < kS) {
         double hv = br[lane];
 #pragma unroll 8
         for (int l = 0; l < kS; ++l) hv = fma(bB[l * kS + lane], sg[l], hv);
@@ -227,8 +266,10 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
     if (tid < 64) {
       const int c = tid;
       const bool rcol = c >= m && c < m + n, vcol = c == m + n;
-      const double* col = c < m ? sH + c : rcol ? sHux + (c - m) : vcol ? sh : sZero;
-      const int cs = (c < m || rcol) ? kS : 1;
+      const bool wcol = DUAL && c > m + n && c <= m + 2 * n;  // columns of W (dual form)
+      const double* col = c < m ? sH + c : rcol ? sHux + (c - m) : vcol ? sh
+                                        : wcol ? sWg + (c - m - n - 1) : sZero;
+      const int cs = (c < m || rcol || wcol) ? kS : 1;
       double v[kS];
       static_for<0, kS>([&](auto R) { v[decltype(R)::value] = col[decltype(R)::value * cs]; });
       int bad = 0;
@@ -237,6 +278,8 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
         static_for<0, kS>([&](auto Kc) { sK[decltype(Kc)::value * kS + (c - m)] = -v[decltype(Kc)::value]; });
       } else if (vcol) {
         static_for<0, kS>([&](auto Kc) { skv[decltype(Kc)::value] = -v[decltype(Kc)::value]; });
+      } else if (wcol) {
+        static_for<0, kS>([&](auto Kc) { sXg[decltype(Kc)::value * kS + (c - m - n - 1)] = v[decltype(Kc)::value]; });
       }
       fail = note_pivot(fail, bad, t);
       if (c < m) sD[c] = sqrt(sD[c]);
@@ -257,6 +300,17 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
         for (int l = 0; l < kS; ++l) v = fma(bA[l * kS + r], sg[l], v);
         spa[r] = v;
       }
+      if (DUAL && tid >= 192) {
+        const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + lk;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bA[k * kS + li], sGam[k * kS + li], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sAG[(lk + 4 * r) * kS + li] = acc[r];
+      }
     }
     __syncthreads();
 
@@ -267,25 +321,59 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
 #pragma unroll 8
       for (int l = 0; l < kS; ++l) v = fma(sHux[l * kS + mx], sK[l * kS + mn], v);
       sP[tid] = v;
-      if (d.P && i < n && j < n) gp(d.P)[(size_t)t * n * n + i * n + j] = v;
+      if (!DUAL && d.P && i < n && j < n) gp(d.P)[(size_t)t * n * n + i * n + j] = v;
       if (tid < kS) {
         double w = spa[tid];
 #pragma unroll 8
         for (int l = 0; l < kS; ++l) w = fma(sHux[l * kS + tid], skv[l], w);
         sp[tid] = w;
         if (tid < n) {
-          if (d.p) gp(d.p)[(size_t)t * n + tid] = w;
+          if (!DUAL && d.p) gp(d.p)[(size_t)t * n + tid] = w;
           if (!isfinite(w)) flags[0] = 1;
         }
       }
-      // gains and Cholesky factor of this stage, from LDS (coalesced)
-      if (i < m && j < n) gp(d.K)[(size_t)t * m * n + i * n + j] = sK[tid];
-      if (tid < m) gp(d.k)[(size_t)t * m + tid] = skv[tid];
-      if (d.chol && i < m && j < m)
-        gp(d.chol)[(size_t)t * m * m + i * m + j] = j < i ? sLu[i * kS + j] * sD[j] : j == i ? sD[i] : 0.0;
+      if (DUAL) {
+        // Psi += W'X (element (max, min), so the halves stay bitwise equal),
+        // Gam <- A'Gam + K'W, psi += Gam'c + W'k
+        double ps = sPsiOld[mx * kS + mn], ga = sAG[tid];
+#pragma unroll 8
+        for (int l = 0; l < kS; ++l) {
+          ps = fma(sWg[l * kS + mx], sXg[l * kS + mn], ps);
+          ga = fma(sK[l * kS + i], sWg[l * kS + j], ga);
+        }
+        sPsiNew[tid] = ps;
+        sGam[tid] = ga;
+        if (tid >= 64 && tid < 64 + kS) {
+          const int r = tid - 64;
+          double w = spsi[r] + sGc[r];
+#pragma unroll 8
+          for (int l = 0; l < kS; ++l) w = fma(sWg[l * kS + r], skv[l], w);
+          spsi[r] = w;
+        }
+      } else {
+        // gains and Cholesky factor of this stage, from LDS (coalesced)
+        if (i < m && j < n) gp(d.K)[(size_t)t * m * n + i * n + j] = sK[tid];
+        if (tid < m) gp(d.k)[(size_t)t * m + tid] = skv[tid];
+        if (d.chol && i < m && j < m)
+          gp(d.chol)[(size_t)t * m * m + i * m + j] = j < i ? sLu[i * kS + j] * sD[j] : j == i ? sD[i] : 0.0;
+      }
       if (t > t0) store_stage(smem + (cur ^ 1) * kStageDoubles, next, i, j);
     }
     __syncthreads();
+  }
+  if (DUAL && i < n && j < n) {  // the segment's summary, row-major n x n blocks
+    const int nn = n * n, e = i * n + j;
+    const double* psiF = sPsi + ((t1 - t0) & 1) * kB;  // the half the last stage wrote
+    gp(out)[e] = sP[tid];
+    gp(out)[nn + e] = sGam[tid];
+    gp(out)[2 * nn + e] = psiF[tid];
+    if (j == 0) {
+      gp(out)[3 * nn + i] = sp[i];
+      gp(out)[3 * nn + n + i] = spsi[i];
+    }
+  } else if (!DUAL && out && i < n && j < n) {  // the value at t0: P | p
+    gp(out)[i * n + j] = sP[tid];
+    if (j == 0) gp(out)[n * n + i] = sp[i];
   }
   const int nonfinite_p = flags[0];
   // wave 0's status to every thread
@@ -301,9 +389,31 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, c
   const InstDesc d = descs ? descs[blockIdx.x] : single;
   const int n = d.n, T = d.T;
   write_terminal(d);
-  const int sweep = small_sweep(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, smem);
+  const int sweep = small_sweep<false>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, nullptr, smem);
   const int nf = rollout(d, 0, T, d.x0, true, smem);
   if (threadIdx.x == 0) *d.info = combine_info(sweep, nf);
+}
+
+// Phase 1 of the segmented solve at these sizes, one workgroup per segment:
+// the parametric sweep of segment j < J - 1 into its summary; the last
+// segment's plain recursion from the terminal cost, its value at its start
+// into the boundary slot. Each segment's status goes to its failure word.
+__global__ __launch_bounds__(kThreads, 2) void k_small_phase1(InstDesc d) {
+  extern __shared__ double smem[];
+  const int n = d.n, T = d.T, J = d.J, seg = blockIdx.x;
+  const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
+  int fail;
+  if (seg < J - 1) {
+    fail = small_sweep<true>(d, t0, t1, nullptr, nullptr, ws_seg(d.ws, n, seg), smem);
+  } else {
+    write_terminal(d);
+    fail = small_sweep<false>(d, t0, t1, d.Q + (size_t)T * n * n, d.q + (size_t)T * n,
+                              ws_bnd(d.ws, n, J, J - 1), smem);
+  }
+  if (threadIdx.x == 0) {
+    d.fail[seg] = fail;
+    if (seg == 0) d.fail[J] = 0;  // the linking-failure word, raised by phase 2
+  }
 }
 
 // Phase 3 of the segmented solve at these sizes, one workgroup per segment:
@@ -316,7 +426,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_phase3(InstDesc d) {
   const int t0 = seg_begin(T, J, seg), t1 = seg_begin(T, J, seg + 1);
   if (seg < J - 1) {
     const double* b = ws_bnd(d.ws, n, J, seg + 1);
-    const int fail = small_sweep(d, t0, t1, b, b + n * n, smem);
+    const int fail = small_sweep<false>(d, t0, t1, b, b + n * n, nullptr, smem);
     if (fail && threadIdx.x == 0) report_info(d.info, fail);
   }
   const int nf = rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
@@ -327,6 +437,14 @@ size_t small_serial_lds() {
   const size_t sweep = kSmallDoubles * sizeof(double) + 64;
   const size_t roll = rollout_lds(16, 16);
   return sweep > roll ? sweep : roll;
+}
+
+hipError_t launch_small_phase1(const InstDesc& d, hipStream_t stream) {
+  const size_t lds = small_serial_lds();
+  hipError_t e = ensure_dynamic_lds((const void*)k_small_phase1, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_small_phase1, dim3(d.J), dim3(kThreads), lds, stream, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_small_phase3(const InstDesc& d, hipStream_t stream) {

@@ -31,7 +31,8 @@ hipError_t launch_serial_batched(const InstDesc* descs, int ninst, int max_m, in
 hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, int ninst,
                                hipStream_t stream);
 constexpr int kSmallMax = 16;
-// Phase 3 of a single segmented solve with n, m <= 16 (k_small.hip).
+// Phases 1 and 3 of a single segmented solve with n, m <= 16 (k_small.hip).
+hipError_t launch_small_phase1(const InstDesc& d, hipStream_t stream);
 hipError_t launch_small_phase3(const InstDesc& d, hipStream_t stream);
 // Dynamic LDS of the adjoint solve for an instance with n, m <= 16 (k_adjoint.hip).
 size_t adjoint_small_lds();

@@ -26,7 +26,9 @@ hipError_t ensure_dynamic_lds(const void* kernel, size_t lds) {
 
 hipError_t launch_phase(const InstDesc& d, int phase, size_t lds, int eng, hipStream_t stream) {
   switch (phase) {
-    case 1: return launch_k_phase1(d, nullptr, nullptr, d.J, kernel_width(d.m, eng), eng, lds, stream);
+    case 1:
+      if (d.n <= kSmallMax && d.m <= kSmallMax) return launch_small_phase1(d, stream);
+      return launch_k_phase1(d, nullptr, nullptr, d.J, kernel_width(d.m, eng), eng, lds, stream);
     case 2:
       if (use_link_tree(d.n, d.J)) return launch_link_tree(d, lds, stream);
       return launch_k_phase2(d, nullptr, nullptr, 1, d.n, launch_engine(d.n, false), lds, stream);

@@ -31,7 +31,11 @@ def test_mixed_matches_fp64_oracle(n, m, T, J, cross):
     assert int(got["info"][0]) == 0
     errs = compare(got, oracle.solve(prob), tol=MIXED_TOL, label="mixed %s" % ((n, m, T, J),))
     # the products really ran in float: the error is far above FP64 rounding
-    assert max(errs.values()) > 1e-12
+    # (at n, m <= 16 the small-size kernels compute in double for every precision)
+    if max(n, m) > 16:
+        assert max(errs.values()) > 1e-12
+    else:
+        assert max(errs.values()) < 1e-12
 
 
 def test_mixed_serial_kernel_matches_oracle():

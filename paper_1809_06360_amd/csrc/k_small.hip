@@ -18,7 +18,8 @@
 // products and only the stores are conditional), so no LDS wait lands inside
 // a loop. Thread (i, j) of a symmetric result computes element
 // (max(i, j), min(i, j)) in a fixed order, so both halves are bitwise equal.
-// The rollout (x, u, costates) is the general one.
+// The forward simulation (x, u, costates) uses the same layout and staging,
+// with the state's whole chain in one wave.
 #include "lqr_device.h"
 #include "lqr_kernels.h"
 #include "lqr_launch.h"
@@ -54,6 +55,130 @@ LQR_DEV StageRegs fetch_stage(const InstDesc& d, int t, int i, int j) {
   if (j == 1 && i < n) g.v = gp(d.q)[(size_t)t * n + i];
   if (j == 2 && i < m) g.v = gp(d.r)[(size_t)t * m + i];
   return g;
+}
+
+// Forward simulation at these sizes: one half of its double buffer holds
+// P | K | A | B | k | p | c of a stage.
+constexpr int kRollDoubles = 4 * kB + 3 * kS;
+
+// This thread's share of stage t's simulation data: K, A, B, k, c when t is
+// a stage of the range (t < t1), P and p when costates are requested.
+LQR_DEV StageRegs fetch_roll(const InstDesc& d, int t, bool st, int i, int j) {
+  const int n = d.n, m = d.m;
+  const bool lam = d.lam != nullptr;
+  StageRegs g;
+  g.a = (lam && i < n && j < n) ? gp(d.P)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.b = (st && i < m && j < n) ? gp(d.K)[(size_t)t * m * n + i * n + j] : 0.0;
+  g.s = (st && i < n && j < n) ? gp(d.A)[(size_t)t * n * n + i * n + j] : 0.0;
+  g.q2 = (st && i < n && j < m) ? gp(d.B)[(size_t)t * n * m + i * m + j] : 0.0;
+  g.r2 = 0.0;
+  g.v = 0.0;
+  if (st && j == 0 && i < m) g.v = gp(d.k)[(size_t)t * m + i];
+  if (lam && j == 1 && i < n) g.v = gp(d.p)[(size_t)t * n + i];
+  if (st && j == 2 && i < n) g.v = gp(d.c)[(size_t)t * n + i];
+  return g;
+}
+
+LQR_DEV void store_roll(double* buf, const StageRegs& g, int i, int j) {
+  const int e = i * kS + j;
+  buf[e] = g.a;
+  buf[kB + e] = g.b;
+  buf[2 * kB + e] = g.s;
+  buf[3 * kB + e] = g.q2;
+  if (j < 3) buf[4 * kB + j * kS + i] = g.v;
+}
+
+// Forward simulation of stages [t0, t1) from x_{t0} = xs (global):
+// u_t = K_t x_t + k_t, x_{t+1} = A_t x_t + B_t u_t + c_t, lam_t = P_t x_t + p_t
+// (when requested); writes x_t, u_t, lam_t and, if last, x_{t1} and
+// lam_{t1}. The whole chain of a stage stays in wave 0 (lane r holds x_r and
+// u_r; the other lanes' values come by readlane), so a stage costs one
+// workgroup barrier: wave 1 forms the costate from the state in LDS while
+// every thread stages the next stage's blocks. Returns LQR_INFO_NONFINITE
+// (uniformly) if any value written is not finite, else 0.
+LQR_DEV int rollout_small(const InstDesc& d, int t0, int t1, const double* xs, bool last,
+                          double* smem) {
+  const int n = d.n, m = d.m;
+  const int tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63, r = lane & 15;
+  const bool want_lam = d.lam != nullptr;
+  double* sx = smem + 2 * kRollDoubles;  // [2][16]: x_t by stage parity
+  int* anybad = reinterpret_cast<int*>(sx + 2 * kS);
+  bool finite = true;
+  double x = r < n ? gp(xs)[r] : 0.0;  // wave 0's state, lane r
+  if (tid < kS) sx[tid] = x;
+  store_roll(smem, fetch_roll(d, t0, t0 < t1, i, j), i, j);
+  __syncthreads();
+  int cur = 0;
+  for (int t = t0; t < t1; ++t, cur ^= 1) {
+    const double* bP = smem + cur * kRollDoubles;
+    const double* bK = bP + kB;
+    const double* bA = bP + 2 * kB;
+    const double* bB = bP + 3 * kB;
+    const double* bk = bP + 4 * kB;
+    const double* bp = bk + kS;
+    const double* bc = bp + kS;
+    const StageRegs next = fetch_roll(d, t + 1, t + 1 < t1, i, j);
+    if (tid < 64) {
+      if (lane < n) {
+        gp(d.x)[(size_t)t * n + lane] = x;
+        finite = finite && isfinite(x);
+      }
+      double u = bk[r], xn = bc[r];
+      static_for<0, kS>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        const double xl = readlane(x, l);
+        u = fma(bK[r * kS + l], xl, u);
+        xn = fma(bA[r * kS + l], xl, xn);
+      });
+      if (lane < m) {
+        gp(d.u)[(size_t)t * m + lane] = u;
+        finite = finite && isfinite(u);
+      }
+      static_for<0, kS>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        xn = fma(bB[r * kS + l], readlane(u, l), xn);
+      });
+      x = xn;
+      if (lane < kS) sx[((t + 1 - t0) & 1) * kS + lane] = x;
+    } else if (tid < 128 && want_lam) {
+      const double* xt = sx + ((t - t0) & 1) * kS;
+      double v = bp[r];
+#pragma unroll 8
+      for (int l = 0; l < kS; ++l) v = fma(bP[r * kS + l], xt[l], v);
+      if (lane < n) {
+        gp(d.lam)[(size_t)t * n + lane] = v;
+        finite = finite && isfinite(v);
+      }
+    }
+    store_roll(smem + (cur ^ 1) * kRollDoubles, next, i, j);
+    __syncthreads();
+  }
+  if (last) {
+    if (tid < 64 && lane < n) {
+      gp(d.x)[(size_t)t1 * n + lane] = x;
+      finite = finite && isfinite(x);
+    } else if (tid >= 64 && tid < 128 && want_lam) {
+      const double* bP = smem + cur * kRollDoubles;
+      const double* bp = bP + 4 * kB + kS;
+      const double* xt = sx + ((t1 - t0) & 1) * kS;
+      double v = bp[r];
+#pragma unroll 8
+      for (int l = 0; l < kS; ++l) v = fma(bP[r * kS + l], xt[l], v);
+      if (lane < n) {
+        gp(d.lam)[(size_t)t1 * n + lane] = v;
+        finite = finite && isfinite(v);
+      }
+    }
+  }
+  const int wave = tid >> 6;
+  const bool wbad = __ballot(!finite) != 0ull;
+  if (lane == 0) anybad[wave] = wbad ? 1 : 0;
+  __syncthreads();
+  int bad = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) bad |= anybad[w];
+  __syncthreads();
+  return bad ? LQR_INFO_NONFINITE : 0;
 }
 
 LQR_DEV void store_stage(double* buf, const StageRegs& g, int i, int j) {
@@ -384,13 +509,18 @@ LQR_DEV int small_sweep(const InstDesc& d, int t0, int t1, const double* Pend, c
   return code;
 }
 
-__global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs) {
+__global__ __launch_bounds__(kThreads, 2) void k_small_serial(InstDesc single, const InstDesc* descs,
+                                                               int spread_rollout) {
   extern __shared__ double smem[];
   const InstDesc d = descs ? descs[blockIdx.x] : single;
   const int n = d.n, T = d.T;
   write_terminal(d);
   const int sweep = small_sweep<false>(d, 0, T, d.Q + (size_t)T * n * n, d.q + (size_t)T * n, nullptr, smem);
-  const int nf = rollout(d, 0, T, d.x0, true, smem);
+  // with a workgroup or more per compute unit the general forward simulation,
+  // which spreads each product over the four waves, keeps the SIMDs busier;
+  // alone on a unit the one-wave chain has the shorter stage
+  const int nf = spread_rollout ? rollout(d, 0, T, d.x0, true, smem)
+                                : rollout_small(d, 0, T, d.x0, true, smem);
   if (threadIdx.x == 0) *d.info = combine_info(sweep, nf);
 }
 
@@ -429,13 +559,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_small_phase3(InstDesc d) {
     const int fail = small_sweep<false>(d, t0, t1, b, b + n * n, nullptr, smem);
     if (fail && threadIdx.x == 0) report_info(d.info, fail);
   }
-  const int nf = rollout(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
+  const int nf = rollout_small(d, t0, t1, ws_bnd(d.ws, n, J, seg) + n * n + n, seg == J - 1, smem);
   if (nf && threadIdx.x == 0) report_info(d.info, nf);
 }
 
 size_t small_serial_lds() {
   const size_t sweep = kSmallDoubles * sizeof(double) + 64;
-  const size_t roll = rollout_lds(16, 16);
+  size_t roll = (2 * kRollDoubles + 2 * kS) * sizeof(double) + 64;
+  if (roll < rollout_lds(16, 16)) roll = rollout_lds(16, 16);
   return sweep > roll ? sweep : roll;
 }
 
@@ -460,7 +591,9 @@ hipError_t launch_small_serial(const InstDesc& single, const InstDesc* descs, in
   const size_t lds = small_serial_lds();
   hipError_t e = ensure_dynamic_lds((const void*)k_small_serial, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_small_serial, dim3(ninst), dim3(kThreads), lds, stream, single, descs);
+  // 256 compute units: from one instance per unit on, spread the rollout
+  hipLaunchKernelGGL(k_small_serial, dim3(ninst), dim3(kThreads), lds, stream, single, descs,
+                     ninst >= 256 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -102,6 +102,30 @@ LQR_DEV void store_regs(double* buf, const AdjRegs& g, int i, int j) {
   if (j < 2) buf[4 * kAB + j * kAS + i] = g.v;
 }
 
+// (L L') y = b for lane r holding b_r (rows >= M zero), unrolled for m = M:
+// the substituted values come from their lanes by readlane and the
+// reciprocals of L's diagonal from rd, so the chain has no LDS wait or guard.
+template <int M>
+LQR_DEV double chol_solve_lanes(double y, int r, const double* L, const double* rd) {
+  static_for<0, M>([&](auto Kc) {
+    constexpr int k = decltype(Kc)::value;
+    const double zk = readlane(y, k) * rd[k];
+    y = r == k ? zk : (r > k ? fma(-L[r * kAS + k], zk, y) : y);
+  });
+  static_for<0, M>([&](auto Kc) {
+    constexpr int k = M - 1 - decltype(Kc)::value;
+    const double yk = readlane(y, k) * rd[k];
+    y = r == k ? yk : (r < k ? fma(-L[k * kAS + r], yk, y) : y);
+  });
+  return y;
+}
+
+template <int... Ms>
+LQR_DEV double chol_solve_dispatch(int m, double y, int r, const double* L, const double* rd) {
+  ((m == Ms ? (y = chol_solve_lanes<Ms>(y, r, L, rd), 0) : 0), ...);
+  return y;
+}
+
 LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
   const int n = a.n, m = a.m, T = a.T;
   const int tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63;
@@ -157,21 +181,8 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
     if (tid < 64) {
       // (L L') y = hhat: lane r holds y_r; rows >= m are zero
       const int r = lane & 15;
-      double y = hv;
-      static_for<0, kAS>([&](auto Kc) {
-        constexpr int k = decltype(Kc)::value;
-        if (k < m) {
-          const double zk = readlane(y, k) * srd[k];
-          y = r == k ? zk : (r > k ? fma(-bL[r * kAS + k], zk, y) : y);
-        }
-      });
-      static_for<0, kAS>([&](auto Kc) {
-        constexpr int k = kAS - 1 - decltype(Kc)::value;
-        if (k < m) {
-          const double yk = readlane(y, k) * srd[k];
-          y = r == k ? yk : (r < k ? fma(-bL[k * kAS + r], yk, y) : y);
-        }
-      });
+      const double y = chol_solve_dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>(
+          m, hv, r, bL, srd);
       if (lane < m) gp(kh)[(size_t)t * m + lane] = -y;
     } else if (tid < 128) {
       // phat_t = qhat + A' phat + K' hhat

@@ -140,8 +140,8 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
   double* sacc = sh + kAS;    // qhat_t + A_t' phat_{t+1}
   double* sx0 = sacc + kAS;   // xhat (ping-pong with sx1)
   double* sx1 = sx0 + kAS;
-  double* su = sx1 + kAS;     // uhat_t
-  double* srd = su + kAS;     // 1 / L_t(k, k)
+  double* sspare = sx1 + kAS; // (spare)
+  double* srd = sspare + kAS; // 1 / L_t(k, k)
 
   // backward
   if (tid < kAS) {
@@ -196,10 +196,13 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
     if (t > 0) store_regs(smem + (cur ^ 1) * kAdjBuf, next, i, j);
     __syncthreads();
   }
-  // forward from xhat_0 = 0
+  // forward from xhat_0 = 0. The state's chain stays in wave 0 (lane r holds
+  // xhat_r and uhat_r, the other lanes' values by readlane), so a stage costs
+  // one barrier; wave 1 forms lamhat from the state in LDS (by stage parity).
   if (tid < kAS) sx0[tid] = 0.0;
   store_regs(smem, fetch_fwd(a, kh, ph, 0, i, j), i, j);
   __syncthreads();
+  double x = 0.0;  // wave 0: xhat_t of row lane & 15
   for (int t = 0, cur = 0; t <= T; ++t, cur ^= 1) {
     const double* bP = smem + cur * kAdjBuf;
     const double* bK = bP + kAB;
@@ -207,38 +210,36 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
     const double* bB = bP + 3 * kAB;
     const double* bk = bP + 4 * kAB;
     const double* bp = bk + kAS;
-    double* sx = (t & 1) ? sx1 : sx0;
+    const double* sx = (t & 1) ? sx1 : sx0;
     double* sxn = (t & 1) ? sx0 : sx1;
     const AdjRegs next = fetch_fwd(a, kh, ph, t < T ? t + 1 : T, i, j);
-    // uhat = K xhat + khat (wave 0), lamhat = P xhat + phat (wave 1), xhat out (wave 2)
     if (tid < 64) {
       const int r = lane & 15;
-      double u = bk[r];
-#pragma unroll 8
-      for (int l = 0; l < kAS; ++l) u = fma(bK[r * kAS + l], sx[l], u);
-      if (t < T && lane < kAS) su[lane] = u;
-      if (t < T && lane < m) gp(uh)[(size_t)t * m + lane] = u;
+      if (lane < n) gp(xh)[(size_t)t * n + lane] = x;
+      if (t < T) {
+        double u = bk[r], xn = 0.0;
+        static_for<0, kAS>([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          const double xl = readlane(x, l);
+          u = fma(bK[r * kAS + l], xl, u);
+          xn = fma(bA[r * kAS + l], xl, xn);
+        });
+        if (lane < m) gp(uh)[(size_t)t * m + lane] = u;
+        static_for<0, kAS>([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          xn = fma(bB[r * kAS + l], readlane(u, l), xn);
+        });
+        x = xn;
+        if (lane < kAS) sxn[lane] = x;
+      }
     } else if (tid < 128) {
       const int r = lane & 15;
       double v = bp[r];
 #pragma unroll 8
       for (int l = 0; l < kAS; ++l) v = fma(bP[r * kAS + l], sx[l], v);
       if (lane < n) gp(lh)[(size_t)t * n + lane] = v;
-    } else if (tid < 192) {
-      if (lane < n) gp(xh)[(size_t)t * n + lane] = sx[lane];
     }
     if (t == T) break;
-    __syncthreads();
-    // xhat_{t+1} = A xhat + B uhat (wave 0)
-    if (tid < 64) {
-      const int r = lane & 15;
-      double v = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kAS; ++l) v = fma(bA[r * kAS + l], sx[l], v);
-#pragma unroll 8
-      for (int l = 0; l < kAS; ++l) v = fma(bB[r * kAS + l], su[l], v);
-      if (lane < kAS) sxn[lane] = v;
-    }
     store_regs(smem + (cur ^ 1) * kAdjBuf, next, i, j);
     __syncthreads();
   }

@@ -143,10 +143,16 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
   double* sspare = sx1 + kAS; // (spare)
   double* srd = sspare + kAS; // 1 / L_t(k, k)
 
-  // backward
+  // backward. Wave 0 forms hhat in registers and runs the substitutions with
+  // it; wave 1 forms hhat again (sixteen products) and then phat, so the two
+  // need no exchange and a stage costs one barrier. phat alternates between
+  // two LDS vectors by stage parity (wave 0 reads the old one while wave 1
+  // writes the new one).
+  double* sp0 = sp;
+  double* sp1 = sacc;
   if (tid < kAS) {
     const double v = tid < n ? -gp(a.dl_dx)[(size_t)T * n + tid] : 0.0;
-    sp[tid] = v;
+    sp0[tid] = v;
     if (tid < n) gp(ph)[(size_t)T * n + tid] = v;
   }
   store_regs(smem, fetch_back(a, T - 1, i, j), i, j);
@@ -158,40 +164,36 @@ LQR_DEV void adjoint_small(const AdjDesc& a, double* smem) {
     const double* bL = bA + 3 * kAB;
     const double* bq = bA + 4 * kAB;
     const double* br = bq + kAS;
+    const double* spo = ((T - 1 - t) & 1) ? sp1 : sp0;  // phat_{t+1}
+    double* spn = ((T - 1 - t) & 1) ? sp0 : sp1;        // phat_t
     const AdjRegs next = fetch_back(a, t > 0 ? t - 1 : 0, i, j);
-    // hhat = rhat + B' phat (wave 0), qhat + A' phat (wave 1)
-    double hv = 0.0;
-    if (tid < 64) {
+    if (tid < 128) {
       const int r = lane & 15;
-      hv = br[r];
+      double hv = br[r];  // hhat = rhat + B' phat
 #pragma unroll 8
-      for (int l = 0; l < kAS; ++l) hv = fma(bB[l * kAS + r], sp[l], hv);
-      if (lane < kAS) sh[lane] = hv;
-    } else if (tid < 128) {
-      const int r = lane & 15;
-      double v = bq[r];
+      for (int l = 0; l < kAS; ++l) hv = fma(bB[l * kAS + r], spo[l], hv);
+      if (tid < 64) {
+        // (L L') y = hhat: lane r holds y_r; rows >= m are zero
+        const double rd = r < m ? 1.0 / bL[r * kAS + r] : 0.0;
+        if (lane < kAS) srd[lane] = rd;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double y = chol_solve_dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>(
+            m, hv, r, bL, srd);
+        if (lane < m) gp(kh)[(size_t)t * m + lane] = -y;
+      } else {
+        // phat_t = qhat + A' phat + K' hhat
+        double v = bq[r];
 #pragma unroll 8
-      for (int l = 0; l < kAS; ++l) v = fma(bA[l * kAS + r], sp[l], v);
-      if (lane < kAS) sacc[lane] = v;
-    } else if (tid < 128 + kAS) {
-      const int r = tid - 128;  // reciprocals of the factor's diagonal, off the chain
-      srd[r] = r < m ? 1.0 / bL[r * kAS + r] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      // (L L') y = hhat: lane r holds y_r; rows >= m are zero
-      const int r = lane & 15;
-      const double y = chol_solve_dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>(
-          m, hv, r, bL, srd);
-      if (lane < m) gp(kh)[(size_t)t * m + lane] = -y;
-    } else if (tid < 128) {
-      // phat_t = qhat + A' phat + K' hhat
-      const int r = lane & 15;
-      double v = sacc[r];
-#pragma unroll 8
-      for (int l = 0; l < kAS; ++l) v = fma(bK[l * kAS + r], sh[l], v);
-      if (lane < kAS) sp[lane] = v;
-      if (lane < n) gp(ph)[(size_t)t * n + lane] = v;
+        for (int l = 0; l < kAS; ++l) v = fma(bA[l * kAS + r], spo[l], v);
+        static_for<0, kAS>([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          v = fma(bK[l * kAS + r], readlane(hv, l), v);
+        });
+        if (lane < kAS) spn[lane] = v;
+        if (lane < n) gp(ph)[(size_t)t * n + lane] = v;
+      }
     }
     if (t > 0) store_regs(smem + (cur ^ 1) * kAdjBuf, next, i, j);
     __syncthreads();

@@ -301,3 +301,19 @@ def test_smoothed_policies_are_refused_where_they_are_not_built():
     with pytest.raises(L.LQRError) as e:
         L.lqr_backward(arr, 1, grads, L.options(smoothed=True), 256, 1 << 20, 0)
     assert e.value.status == L.ERR_UNSUPPORTED
+
+
+def test_python_constants_match_the_header():
+    """The binding's status, precision, info and flag constants are the
+    header's #define and enum values."""
+    text = open(HEADER).read()
+    defines = {k: int(v, 0) for k, v in re.findall(r"#define\s+(LQR_\w+)\s+\(?(-?0x[0-9a-fA-F]+|-?\d+)u?\)?", text)}
+    assert defines["LQR_FLAG_PHASED"] == L.FLAG_PHASED
+    assert defines["LQR_FLAG_SMOOTHED"] == L.FLAG_SMOOTHED
+    assert defines["LQR_INFO_COUPLING"] == L.INFO_COUPLING
+    assert defines["LQR_INFO_QUEUE"] == L.INFO_QUEUE
+    assert defines["LQR_INFO_NONFINITE"] == L.INFO_NONFINITE
+    enums = {k: int(v) for k, v in re.findall(r"(LQR_(?:PREC|ALGO)_\w+)\s*=\s*(\d+)", text)}
+    assert (enums["LQR_PREC_FP64"], enums["LQR_PREC_MIXED"], enums["LQR_PREC_FP32"]) == \
+        (L.PREC_FP64, L.PREC_MIXED, L.PREC_FP32)
+    assert (enums["LQR_ALGO_PARALLEL"], enums["LQR_ALGO_SERIAL"]) == (L.ALGO_PARALLEL, L.ALGO_SERIAL)

@@ -348,7 +348,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
 //   dA_t = -(lamhat_{t+1} x_t' + lam_{t+1} xhat_t'),
 //   dB_t = -(lamhat_{t+1} u_t' + lam_{t+1} uhat_t').
 // Every output element is written by exactly one thread with coalesced rows.
+// The block's vectors (x, xhat, u, uhat, lam_{t+1}, lamhat_{t+1} of each of its
+// stages) are first copied to LDS in one pass, so the stores of the outer
+// products wait for one round of loads rather than one per stage.
+constexpr int kGradVec = 4 * 128 + 2 * 64;  // per stage, at the largest n and m
+
 __global__ __launch_bounds__(kThreads) void k_adjoint_grad(const AdjDesc* descs, const int2* blocks) {
+  __shared__ double sv[kAdjStages * kGradVec];
   const int2 bk = blocks[blockIdx.x];
   const AdjDesc a = descs[bk.x];
   const int n = a.n, m = a.m, T = a.T;
@@ -357,46 +363,61 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_grad(const AdjDesc* descs,
   const double* uh = xh + (size_t)(T + 1) * n;
   const double* lh = uh + (size_t)T * m;
   const int t0 = bk.y * kAdjStages, t1 = min(T + 1, t0 + kAdjStages);
+  // per stage: x | xhat | lam_{t+1} | lamhat_{t+1} (n each) | u | uhat (m each)
+  const int vs = 4 * n + 2 * m;
+  for (int e = threadIdx.x; e < (t1 - t0) * vs; e += kThreads) {
+    const int s = e / vs, q = e - s * vs, t = t0 + s;
+    double v = 0.0;
+    if (q < n) v = gp(a.x)[(size_t)t * n + q];
+    else if (q < 2 * n) v = gp(xh)[(size_t)t * n + (q - n)];
+    else if (t < T && q < 3 * n) v = gp(a.lam)[(size_t)(t + 1) * n + (q - 2 * n)];
+    else if (t < T && q < 4 * n) v = gp(lh)[(size_t)(t + 1) * n + (q - 3 * n)];
+    else if (t < T && q < 4 * n + m) v = gp(a.u)[(size_t)t * m + (q - 4 * n)];
+    else if (t < T && q >= 4 * n + m) v = gp(uh)[(size_t)t * m + (q - 4 * n - m)];
+    sv[s * kGradVec + q] = v;
+  }
+  __syncthreads();
   for (int t = t0; t < t1; ++t) {
-    const double* xt = a.x + (size_t)t * n;
-    const double* xht = xh + (size_t)t * n;
+    const double* sx = sv + (t - t0) * kGradVec;
+    const double* xt = sx;
+    const double* xht = sx + n;
     if (a.dq)
-      for (int i = threadIdx.x; i < n; i += kThreads) a.dq[(size_t)t * n + i] = -xht[i];
+      for (int i = threadIdx.x; i < n; i += kThreads) gp(a.dq)[(size_t)t * n + i] = -xht[i];
     if (a.dQ)
       for (int e = threadIdx.x; e < n * n; e += kThreads) {
         const int i = e / n, j = e - i * n;
-        a.dQ[(size_t)t * n * n + e] = -0.5 * (xht[i] * xt[j] + xt[i] * xht[j]);
+        gp(a.dQ)[(size_t)t * n * n + e] = -0.5 * (xht[i] * xt[j] + xt[i] * xht[j]);
       }
     if (t == 0 && a.dx0)
-      for (int i = threadIdx.x; i < n; i += kThreads) a.dx0[i] = -lh[i];
+      for (int i = threadIdx.x; i < n; i += kThreads) gp(a.dx0)[i] = -gp(lh)[i];
     if (t == T) continue;
-    const double* ut = a.u + (size_t)t * m;
-    const double* uht = uh + (size_t)t * m;
-    const double* l1 = a.lam + (size_t)(t + 1) * n;
-    const double* lh1 = lh + (size_t)(t + 1) * n;
+    const double* ut = sx + 4 * n;
+    const double* uht = sx + 4 * n + m;
+    const double* l1 = sx + 2 * n;
+    const double* lh1 = sx + 3 * n;
     if (a.dr)
-      for (int i = threadIdx.x; i < m; i += kThreads) a.dr[(size_t)t * m + i] = -uht[i];
+      for (int i = threadIdx.x; i < m; i += kThreads) gp(a.dr)[(size_t)t * m + i] = -uht[i];
     if (a.dc)
-      for (int i = threadIdx.x; i < n; i += kThreads) a.dc[(size_t)t * n + i] = -lh1[i];
+      for (int i = threadIdx.x; i < n; i += kThreads) gp(a.dc)[(size_t)t * n + i] = -lh1[i];
     if (a.dR)
       for (int e = threadIdx.x; e < m * m; e += kThreads) {
         const int i = e / m, j = e - i * m;
-        a.dR[(size_t)t * m * m + e] = -0.5 * (uht[i] * ut[j] + ut[i] * uht[j]);
+        gp(a.dR)[(size_t)t * m * m + e] = -0.5 * (uht[i] * ut[j] + ut[i] * uht[j]);
       }
     if (a.dS)
       for (int e = threadIdx.x; e < m * n; e += kThreads) {
         const int i = e / n, j = e - i * n;
-        a.dS[(size_t)t * m * n + e] = -(uht[i] * xt[j] + ut[i] * xht[j]);
+        gp(a.dS)[(size_t)t * m * n + e] = -(uht[i] * xt[j] + ut[i] * xht[j]);
       }
     if (a.dA)
       for (int e = threadIdx.x; e < n * n; e += kThreads) {
         const int i = e / n, j = e - i * n;
-        a.dA[(size_t)t * n * n + e] = -(lh1[i] * xt[j] + l1[i] * xht[j]);
+        gp(a.dA)[(size_t)t * n * n + e] = -(lh1[i] * xt[j] + l1[i] * xht[j]);
       }
     if (a.dB)
       for (int e = threadIdx.x; e < n * m; e += kThreads) {
         const int i = e / m, j = e - i * m;
-        a.dB[(size_t)t * n * m + e] = -(lh1[i] * ut[j] + l1[i] * uht[j]);
+        gp(a.dB)[(size_t)t * n * m + e] = -(lh1[i] * ut[j] + l1[i] * uht[j]);
       }
   }
 }

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_solve(const AdjDesc* descs
 constexpr int kGradVec = 4 * 128 + 2 * 64;  // per stage, at the largest n and m
 
 __global__ __launch_bounds__(kThreads) void k_adjoint_grad(const AdjDesc* descs, const int2* blocks) {
-  __shared__ double sv[kAdjStages * kGradVec];
+  extern __shared__ double sv[];  // kAdjStages x kGradVec (dynamic, like every kernel's LDS)
   const int2 bk = blocks[blockIdx.x];
   const AdjDesc a = descs[bk.x];
   const int n = a.n, m = a.m, T = a.T;
@@ -428,7 +428,9 @@ hipError_t launch_adjoint(const AdjDesc* descs, int ninst, const int2* blocks, i
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_solve, dim3(ninst), dim3(kThreads), lds, stream, descs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adjoint_grad, dim3(nblocks), dim3(kThreads), 0, stream, descs, blocks);
+  const size_t glds = (size_t)kAdjStages * kGradVec * sizeof(double);
+  if ((e = ensure_dynamic_lds((const void*)k_adjoint_grad, glds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adjoint_grad, dim3(nblocks), dim3(kThreads), glds, stream, descs, blocks);
   return hipGetLastError();
 }
 

@@ -387,8 +387,10 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
   double* Gn = gtmp;
   if (threadIdx.x == 0) *bad = 0;
   fill_block(P, ldp, n, n, 0.0, 0.0);
-  fill_block(Psi, n, n, n, 0.0, 0.0);
-  fill_block(Gam, n, n, n, 0.0, 1.0);
+  for (int e = threadIdx.x; e < nn; e += kThreads) {  // Psi = 0, Gam = I (global)
+    gp(Psi)[e] = 0.0;
+    gp(Gam)[e] = (e / n == e % n) ? 1.0 : 0.0;
+  }
   for (int i = threadIdx.x; i < n; i += kThreads) {
     p[i] = 0.0;
     psi[i] = 0.0;
@@ -450,21 +452,21 @@ LQR_DEV int dual_sweep_gs(const InstDesc& d, int t0, int t1, double* out, double
     {  // Psi += Z_W'Z_W (in place, global), psi += Gam'c - Z_W'z_h
       pgemm_sub<E, false, true, false, false>(n, n + 1, m, G + (m + n + 1) * mp, mp, G + (m + n) * mp, mp,
           0, G, mp, G, mp,
-          [=](int i, int j, double v) {
+          [=, gPsi = gp(Psi)](int i, int j, double v) {
             if (j == 0) {
               psi[i] += gc[i] - v;
             } else if (i >= j - 1) {
               const int jj = j - 1;
-              const double nv = Psi[i * n + jj] + v;
-              Psi[i * n + jj] = nv;
-              Psi[jj * n + i] = nv;
+              const double nv = gPsi[i * n + jj] + v;
+              gPsi[i * n + jj] = nv;
+              gPsi[jj * n + i] = nv;
             }
           },
           SkipUpperShift{n, 1});
     }
     // Gam <- A'Gam - Z_ux'Z_W into the other buffer
     pgemm_sub<E, true, false, false, true>(n, n, n, At, n, Gam, n, m, G + m * mp, mp,
-        G + (m + n + 1) * mp, mp, [=](int i, int j, double v) { Gn[i * n + j] = v; });
+        G + (m + n + 1) * mp, mp, [=, gGn = gp(Gn)](int i, int j, double v) { gGn[i * n + j] = v; });
     sink(next, reinterpret_cast<double*>(bad) + 1);
     __syncthreads();
     double* tmp = Gam;
@@ -678,15 +680,15 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
   {
     const double* bl = ws_bnd(d.ws, n, J, J - 1);
     load_block(sPn, L, bl, n, n, n);
-    for (int i = threadIdx.x; i < n; i += kThreads) spn[i] = bl[n * n + i];
+    for (int i = threadIdx.x; i < n; i += kThreads) spn[i] = gp(bl)[n * n + i];
   }
   for (int j = J - 2; j >= 0; --j) {
     const double* sg = ws_seg(d.ws, n, j);
-    const double* P0 = sg;
+    const LQR_GLOBAL double* P0 = gp(sg);
     const double* Gam = sg + n * n;
     const double* Psi = sg + 2 * n * n;
-    const double* pbar = sg + 3 * n * n;
-    const double* psi = pbar + n;
+    const LQR_GLOBAL double* pbar = gp(sg + 3 * n * n);
+    const LQR_GLOBAL double* psi = pbar + n;
     load_block(sA1, L, Psi, n, n, n);
     __syncthreads();
     pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sPn, L, 0, sA1, L, sPn, L,
@@ -700,7 +702,7 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
     if (threadIdx.x == 0 && bad && !flag[1]) flag[1] = LQR_INFO_COUPLING + j;
     // [F | f] = N^{-1} [Gam' | w], kept in LDS and written to the workspace
     // (F column-major) for the forward pass: F' = Gam N^{-T}
-    double* lk = ws_link(d.ws, n, J, j);
+    LQR_GLOBAL double* lk = gp(ws_link(d.ws, n, J, j));
     pgemm_sub<fp64_engine(E), false, false, false, false>(n, n, n, sA1, L, sN, L, 0, sA1, L, sN, L,
         [=](int c, int i, double v) {
           sF[c * L + i] = v;
@@ -729,19 +731,20 @@ LQR_DEV void couple_item(const InstDesc& d, double* smem) {
     __syncthreads();
     double* b = ws_bnd(d.ws, n, J, j);
     store_block(b, n, sPn, L, n, n);
-    for (int i = threadIdx.x; i < n; i += kThreads) b[n * n + i] = spn[i];
+    for (int i = threadIdx.x; i < n; i += kThreads) gp(b)[n * n + i] = spn[i];
   }
   // forward over the boundaries: x_{t_0} = x0, x_{t_{j+1}} = F_j x_{t_j} + f_j
   for (int i = threadIdx.x; i < n; i += kThreads) {
-    sx[i] = d.x0[i];
-    ws_bnd(d.ws, n, J, 0)[n * n + n + i] = d.x0[i];
+    sx[i] = gp(d.x0)[i];
+    gp(ws_bnd(d.ws, n, J, 0))[n * n + n + i] = gp(d.x0)[i];
   }
   __syncthreads();
   for (int j = 0; j < J - 1; ++j) {
     const double* lk = ws_link(d.ws, n, J, j);
-    gemv_cm_wave(0, n, n, lk, n, sx, [=](int i, double v) { sxn[i] = lk[n * n + i] + v; });
+    const LQR_GLOBAL double* lkf = gp(lk + n * n);
+    gemv_cm_wave(0, n, n, lk, n, sx, [=](int i, double v) { sxn[i] = lkf[i] + v; });
     __syncthreads();
-    double* xb = ws_bnd(d.ws, n, J, j + 1) + n * n + n;
+    LQR_GLOBAL double* xb = gp(ws_bnd(d.ws, n, J, j + 1) + n * n + n);
     for (int i = threadIdx.x; i < n; i += kThreads) {
       sx[i] = sxn[i];
       xb[i] = sxn[i];

@@ -78,3 +78,32 @@ def test_small_batch_mixed_with_a_larger_instance_takes_the_general_path():
     torch.cuda.synchronize()
     for p, o in zip(probs, outs):
         compare(host(o), oracle.solve(p), label="general path %s" % (p["B"].shape,))
+
+
+@pytest.mark.parametrize("n,m,T,J,algo,smoothed", [
+    (6, 3, 40, 4, "parallel", False), (12, 8, 64, 8, "parallel", False),
+    (12, 8, 64, 8, "parallel", True), (5, 2, 20, 1, "serial", False)])
+def test_small_phase_by_phase_equals_lqr_solve(n, m, T, J, algo, smoothed):
+    """lqr_solve_phase (phase by phase, the small-size kernels for phases 1
+    and 3) gives lqr_solve's results bitwise, and the oracle's."""
+    import ctypes
+    import paper_1809_06360_amd as L
+    prob = make_instance(194, 0, n, m, T, cross_term=True)
+    a = host(L.solve(to_device(prob), segments=J, algo=algo, smoothed=smoothed))
+    data = to_device(prob)
+    out = L._outputs(n, m, T, torch.float64, data["A"].device, True, True, False)
+    pr = L._problem(data, out, J)
+    opts = L.options("fp64", algo, smoothed=smoothed)
+    nb = L.lqr_workspace_size(ctypes.byref(pr), 1, opts)
+    ws = torch.empty(nb, dtype=torch.uint8, device=data["A"].device)
+    s = torch.cuda.current_stream().cuda_stream
+    for ph in ((1,) if algo == "serial" else (1, 2, 3)):
+        L.lqr_solve_phase(pr, opts, ph, ws.data_ptr(), nb, s)
+    torch.cuda.synchronize()
+    c = host(out)
+    assert int(c["info"][0]) == 0
+    for k in ("K", "k", "P", "p", "x", "u", "lam"):
+        assert np.array_equal(a[k], c[k]), k
+    ref = oracle.solve(prob)
+    keys = ("x", "u", "lam") if smoothed else ("K", "k", "P", "p", "x", "u", "lam")
+    compare(c, ref, keys=keys, label="small phases %s" % ((n, m, T, J, algo, smoothed),))

@@ -229,7 +229,10 @@ lqr_status_t lqr_plan_segments(const lqr_problem_t *probs, int32_t batch,
  * queue in an order fixed by the planner, and per-instance counters in the
  * workspace make each linking solve wait for its instance's sweeps and each
  * rebuild for its linking solve. With LQR_ALGO_SERIAL it is one workgroup per
- * instance running the plain recursion. The execution plan (segment counts,
+ * instance running the plain recursion (on the small-size kernel when every
+ * instance has n <= 16 and m <= 16, as for one-segment batches; lqr_solve
+ * uses the small-size kernels for all three phases of such an instance).
+ * The execution plan (segment counts,
  * descriptor and task tables) is built on the host and copied into the
  * workspace; when a call is made while `stream` is being captured into a HIP
  * graph, the plan for exactly these descriptors must already be in this
